@@ -1,0 +1,223 @@
+"""Throughput of the DT back-propagation + gridding hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dt_ewald_128]
+
+One step = one full reconstruction (all views: contrast, DFT, eq. 11 filter,
+propagation to every depth plane, inverse FFTs, trilinear gridding) of the
+workload, images already resident in HBM.  Prints one JSON line.
+
+The roofline object is computed for the kernel with the largest share of the
+step, from library-side HIP event timing (two events around every launch, on
+the launch's stream) over a second timed region of the same K steps.  The CPU
+baseline is the FP64 oracle on a bounded view subset of the same workload,
+timed on the host (rank 0, N=1 only); the same subset gives the rel-L2 of the
+GPU partial sum against the oracle over all N^3 voxels.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK = 157.3e3       # GFLOP/s (packed FMA); plain lane ops: 256 CU * 64 lanes * 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dt_ewald_128")
+    ap.add_argument("--angle-batch", type=int, default=0)
+    ap.add_argument("--cpu-views", type=int, default=48, help="views in the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    """A plain copy of known size, run under the same profiler command as the bench so
+    that its FETCH_SIZE / WRITE_SIZE readings calibrate the counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}), flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fft.hpp", "tomo_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2206_09151_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool) -> float:
+    """Compulsory HBM bytes of one launch over nb views."""
+    N, M, K = w.n_vox, w.M, w.K
+    if kind == "spectra":   # image read + filter table read + Q write (16 B per coefficient each)
+        return nb * (4.0 * M * M + 16.0 * M * M + 16.0 * M * M)
+    if kind == "planes":    # Q read once per view + plane stack write
+        return nb * (16.0 * M * M + 4.0 * M * K * M)
+    if kind == "grid":      # plane stack read + volume write (+ read when accumulating)
+        return nb * 4.0 * M * K * M + (4.0 if first_batch else 8.0) * N ** 3
+    raise KeyError(kind)
+
+
+def read_traffic(kind: str, src_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from synth import workloads
+    from paper_2206_09151_amd import tomo
+
+    w = workloads.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    ph, dirs, dist, imgs64 = workloads.make_workload(w, device="cuda")
+    imgs = imgs64.astype(np.float32)
+    gen_s = time.time() - t0
+    print(f"[bench] inputs {w.name}: {imgs.shape} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    d_img = torch.from_numpy(imgs).to(dev)
+    vol = torch.empty((w.n_vox,) * 3, dtype=torch.float32, device=dev)
+    params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
+                         sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
+                         weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in,
+                         angle_batch=args.angle_batch)
+    stream = torch.cuda.current_stream()
+    plan = tomo.Plan(params, dirs, dist, stream=stream)
+    batch = plan.batch
+
+    for _ in range(args.warmup):
+        plan.reconstruct(d_img, vol, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        plan.reconstruct(d_img, vol, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    ms = elapsed * 1e3 / args.steps
+    updates = float(w.n_vox) ** 3 * w.n_views
+    value = updates / (ms * 1e-3)
+    print(f"[bench] {ms:.3f} ms/step, {value:.4g} updates/s (batch {batch})", file=sys.stderr, flush=True)
+
+    roofline = None
+    kernels = None
+    if not args.no_kernel_timing:
+        plan.timing(True)
+        plan.timing_read(reset=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            plan.reconstruct(d_img, vol, stream=stream)
+        torch.cuda.synchronize()
+        ms_timed = (time.perf_counter() - t) * 1e3 / args.steps
+        plan.timing(False)
+        k = plan.timing_read(reset=True)
+        n_batches = -(-w.n_views // batch)
+        kernels = {}
+        for kind, (tot, cnt) in k.items():
+            if cnt == 0:
+                continue
+            # bytes of all launches of one step (the first batch writes V without reading it)
+            step_bytes = sum(algorithmic_bytes(kind, w, min(batch, w.n_views - b * batch), b == 0)
+                             for b in range(n_batches))
+            avg_ms = tot / cnt
+            kernels[kind] = {"avg_ms": avg_ms, "launches_per_step": cnt / args.steps,
+                             "ms_per_step": tot / args.steps,
+                             "algorithmic_bytes_per_launch": step_bytes / n_batches,
+                             "GBps": step_bytes / n_batches / (avg_ms * 1e-3) / 1e9}
+        dom = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
+        src_hash = kernel_source_hash()
+        achieved = kernels[dom]["GBps"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": read_traffic(dom, src_hash),
+                    "ms_per_step_with_events": round(ms_timed, 4), "kernel_source_hash": src_hash}
+        print(f"[bench] kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
+
+    cpu = None
+    rel_l2 = None
+    if not args.no_cpu:
+        import oracle
+        nv = min(args.cpu_views, w.n_views)
+        views = np.arange(nv)
+        geo = oracle.Geometry(w.n_vox, w.M, w.K if w.ewald else 1, w.voxel, w.wavelength, w.sigma, w.epsilon,
+                              ewald=w.ewald, weight_mode=w.weight_mode, eps_sampling=w.eps_sampling,
+                              i_in=w.i_in)
+        t = time.perf_counter()
+        ref = oracle.reconstruct_views(imgs.astype(np.float64), dirs, dist, geo, views=views)
+        cpu_s = time.perf_counter() - t
+        cpu = {"value": float(w.n_vox) ** 3 * nv / cpu_s, "unit": "voxel*angle updates/s", "cores": 1,
+               "kind": "oracle", "sample": f"{nv} of {w.n_views} views, full {w.n_vox}^3 volume, "
+                                           f"{cpu_s:.1f} s (numpy FP64, single thread)"}
+        # the same views through the HIP path (stage entry points), compared over all voxels
+        part = torch.zeros_like(vol)
+        st = torch.empty(plan.stack_shape(min(batch, nv)), dtype=torch.float32, device=dev)
+        for first in range(0, nv, batch):
+            nb = min(batch, nv - first)
+            plan.backpropagate(d_img[first:first + nb].contiguous(), first, nb, st, stream=stream)
+            plan.grid(st, first, nb, part, stream=stream)
+        torch.cuda.synchronize()
+        got = part.cpu().numpy().astype(np.float64)
+        rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"[bench] oracle {cpu_s:.1f}s on {nv} views; rel-L2 {rel_l2:.3g}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "voxel*angle updates/s (DT backprop+gridding)",
+        "value": value,
+        "unit": "voxel*angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_vox": w.n_vox, "n_pix": w.M, "n_planes": w.K,
+                   "n_views": w.n_views, "ewald": w.ewald, "weight_mode": w.weight_mode,
+                   "angle_batch": batch, "updates_per_step": updates},
+        "rel_l2_vs_fp64": rel_l2,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

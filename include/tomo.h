@@ -1,0 +1,180 @@
+/*
+ * tomo.h -- C ABI of the MI355X (gfx950) reconstruction library libtomo.so.
+ *
+ * Method: Gureyev, Brown, Quiney, Allen, "Fast unified reconstruction algorithm
+ * for conventional, phase-contrast and diffraction tomography", arXiv:2206.09151.
+ * For every view n the library forms the log-contrast g = ln(I_n / I_in)
+ * (eq. 4 left side), its 2D DFT, applies the Tikhonov-regularised CTF inverse of
+ * eq. (11) with a density weight W_n(q) that replaces 1/n_q (text after eq. 11),
+ * back-propagates the result to K depth planes with the Fresnel propagator of
+ * eq. (3) (the Ewald paraboloid of eqs. 8/10), keeps the real part, and grids
+ * the plane stacks into the voxel volume by trilinear interpolation (eight
+ * neighbours, weights summing to one; text after eq. 11), summed over views.
+ * With ewald = 0 the bracket's imaginary part and the depth planes are dropped
+ * (eq. 13: phase-contrast / conventional CT).
+ *
+ * Conventions (all calls):
+ *   - Volume V: float32 [N][N][N], index [iz][iy][ix] (x fastest).  Voxel
+ *     (iz,iy,ix) sits at ((ix,iy,iz) - (N-1)/2) * voxel_size, relative to the
+ *     rotation centre.
+ *   - Image n: float32 [M][M], index [row][col]; pixel (a,b) sits at
+ *     x' = (b-(M-1)/2) dx along u_n, y' = (a-(M-1)/2) dx along v_n.  Images are
+ *     flat-field normalised intensities; every value must be finite and > 0.
+ *   - View frame: d_n is the unit illumination direction (beam along +d_n);
+ *     v_n is the lab y axis projected onto the detector plane (lab x if d_n is
+ *     within 1e-6 of +-y) unless vaxes gives it; u_n = v_n x d_n.
+ *   - Depth planes z'_j = (j - (K-1)/2) * voxel_size, j = 0..K-1.  dist[n] = R_n
+ *     is measured from the plane z' = 0 through the rotation centre.
+ *   - Plane stack (tomo_backpropagate output / tomo_grid input): float32
+ *     [nb][M][K][M], index [view][row][plane][col]; with ewald = 0, K = 1.
+ *   - Device pointers must be 256-byte aligned device allocations owned by the
+ *     caller; they are never freed or retained by the library.
+ *   - Streams are hipStream_t passed as void*; NULL means the null stream.
+ *     Every call enqueues asynchronously on its stream except where stated.
+ *     A plan is used by one stream at a time; there is no global state.
+ *
+ * Errors: every call returns tomo_status and never aborts or throws.
+ *   TOMO_EINVAL       bad argument (null pointer, non-unit direction, bad range)
+ *   TOMO_ENOMEM       device allocation failed or would exceed max_workspace_bytes
+ *   TOMO_EDEVICE      a HIP call failed (message in tomo_last_error)
+ *   TOMO_EDOMAIN      an image value was <= 0 or not finite (detected on the
+ *                     device; reported by the next synchronising call)
+ *   TOMO_EUNSUPPORTED size or option not implemented (message says which)
+ */
+#ifndef TOMO_H
+#define TOMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tomo_plan_s* tomo_plan_t;
+
+typedef enum {
+  TOMO_OK = 0,
+  TOMO_EINVAL = 1,
+  TOMO_ENOMEM = 2,
+  TOMO_EDEVICE = 3,
+  TOMO_EDOMAIN = 4,
+  TOMO_EUNSUPPORTED = 5
+} tomo_status;
+
+/* Density weight W_n(q) replacing 1/n_q of eq. (11) (text after eq. 11, Section 4):
+ *   TOMO_RAMP_AXIS  a_n |q.u_n|: single-axis scan about y (every d_n.y == 0 within
+ *                   1e-9); a_n = trapezoid weight of the view's angle folded into
+ *                   [0, pi) (pi/n for uniform 180- or 360-degree scans).
+ *   TOMO_RAMP_ISO   2|q|/n: directions uniform on the sphere.
+ *   TOMO_SAMPLING   M^2/(N^3 dx) * S/(S^2 + eps_sampling) with S the trilinear
+ *                   sampling matrix on the N^3 Fourier grid (spacing 1/(N dx)),
+ *                   interpolated at the sample; every sample and its point
+ *                   reflection add half their weights; zero off the grid. */
+typedef enum { TOMO_RAMP_AXIS = 0, TOMO_RAMP_ISO = 1, TOMO_SAMPLING = 2 } tomo_weight_mode;
+
+/* Storage type of the plane stack.  Only TOMO_F32 is implemented. */
+typedef enum { TOMO_F32 = 0, TOMO_BF16 = 1, TOMO_F16 = 2 } tomo_dtype;
+
+typedef struct {
+  int32_t n_vox;          /* N: volume edge in voxels (>= 2) */
+  int32_t n_pix;          /* M: image edge in pixels; 0 -> N */
+  int32_t n_planes;       /* K: depth planes per view; 0 -> N (ewald = 1); forced to 1 when ewald = 0 */
+  int32_t n_angles;       /* n: number of views (>= 1) */
+  double voxel_size;      /* dx [m], voxel edge = detector pixel (> 0) */
+  double wavelength;      /* lambda [m] (> 0) */
+  double sigma;           /* beta/delta of the monomorphous object (finite); omega = atan(sigma) */
+  double epsilon;         /* Tikhonov epsilon of eq. (11) (> 0) */
+  double eps_sampling;    /* regulariser of S^-1 in TOMO_SAMPLING (>= 0; 0 -> 1e-3) */
+  double i_in;            /* flat-field intensity I_in (> 0; 0 -> 1) */
+  int32_t ewald;          /* 1: eq. (11) with depth planes; 0: eq. (13), one plane */
+  int32_t weight_mode;    /* tomo_weight_mode */
+  int32_t plane_dtype;    /* tomo_dtype; TOMO_F32 */
+  int32_t angle_batch;    /* views per internal batch of tomo_reconstruct; 0 -> automatic */
+  size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
+                                 when plan tables + workspace would exceed it */
+} tomo_params;
+
+/* Create a plan: validates parameters, builds the view frames, the density
+ * weights, the per-view filter table C W_n H_n (computed in FP64 on the device,
+ * stored FP32) and the propagator table, and allocates the workspace.
+ *   p      parameters (host; copied)
+ *   dirs   host double [n][3], unit illumination directions (|norm - 1| <= 1e-9)
+ *   vaxes  host double [n][3] detector row axes, or NULL for the default rule
+ *   dist   host double [n], R_n (finite)
+ *   stream hipStream_t the plan's set-up work runs on (synchronised before return)
+ *   out    receives the plan; untouched on error.
+ * Supported: M in {16, 32, 48, 64, 80, 96, 128}; N in [2, 1024]; K in [1, 2N]. */
+tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* vaxes,
+                      const double* dist, void* stream, tomo_plan_t* out);
+
+/* Back-propagate views [first, first+nb): contrast, 2D DFT, filter (eq. 11),
+ * propagation to every depth plane (eq. 3), real part.  Writes the plane stacks
+ * d_planes (device, float32 [nb][M][K][M], fully overwritten).
+ * d_images: device float32 [nb][M][M], the images of those views.  Asynchronous:
+ * an invalid image value raises TOMO_EDOMAIN at the next tomo_sync/tomo_reconstruct.
+ * Uses the plan's spectrum slots of those views (calls on one plan are serial). */
+tomo_status tomo_backpropagate(tomo_plan_t plan, const float* d_images, int32_t first, int32_t nb,
+                               void* d_planes, void* stream);
+
+/* Grid plane stacks of views [first, first+nb) into the volume: for every voxel
+ * the trilinear value of each view's stack at the voxel's view-frame position
+ * (taps outside the stack count as zero) is added to d_volume (device float32
+ * [N][N][N], accumulated: V += sum over the nb views, in ascending view order).
+ * Deterministic: no atomics. */
+tomo_status tomo_grid(tomo_plan_t plan, const void* d_planes, int32_t first, int32_t nb,
+                      float* d_volume, void* stream);
+
+/* Whole reconstruction: d_volume (device float32 [N][N][N]) is overwritten with
+ * the sum over all n views, processed in internal batches of the plan's batch
+ * size.  d_images: device float32 [n][M][M].  Synchronises the stream once at
+ * the end to report TOMO_EDOMAIN. */
+tomo_status tomo_reconstruct(tomo_plan_t plan, const float* d_images, float* d_volume, void* stream);
+
+/* Synchronise the stream and report any device-detected domain error since the
+ * last report (TOMO_EDOMAIN) or TOMO_OK. */
+tomo_status tomo_sync(tomo_plan_t plan, void* stream);
+
+/* Filtered spectra of views [first, first+nb) for inspection: d_out (device
+ * float32 complex, [nb][M][M][2], index [view][ky][kx][re/im]) receives
+ * P_n = C W_n H_n DFT2(ln(I_n/I_in)) as defined by eq. (11) (no 1/M^2 factor). */
+tomo_status tomo_filtered_spectra(tomo_plan_t plan, const float* d_images, int32_t first,
+                                  int32_t nb, float* d_out, void* stream);
+
+/* Per-kernel timing (tracing).  While enabled, every kernel launch of the plan is
+ * bracketed by two HIP events recorded on the launch's stream.  Kinds:
+ *   0 = contrast + DFT + filter (spectra), 1 = depth planes (inverse FFTs),
+ *   2 = gridding.  tomo_timing_read synchronises on the recorded events, adds
+ * their elapsed times to the totals, and returns, per kind, total milliseconds
+ * and launch counts since the last reset (reset != 0 clears them afterwards).
+ * total_ms and launches are host arrays of 3 entries. */
+tomo_status tomo_timing_enable(tomo_plan_t plan, int32_t enable);
+tomo_status tomo_timing_read(tomo_plan_t plan, double* total_ms, int64_t* launches, int32_t reset);
+
+/* Bytes of plan tables + workspace that tomo_plan would allocate for p (0 if p is invalid). */
+size_t tomo_workspace_bytes(const tomo_params* p);
+
+/* Views per internal batch of tomo_reconstruct (plane stacks held at once). */
+int32_t tomo_batch_capacity(tomo_plan_t plan);
+
+/* Bytes of nb plane stacks in the layout above. */
+size_t tomo_stack_bytes(tomo_plan_t plan, int32_t nb);
+
+/* Static description of a status code. */
+const char* tomo_status_string(tomo_status s);
+
+/* Message of the last failing call on this plan ("" if none).  Valid until the
+ * next call on the plan. */
+const char* tomo_last_error(tomo_plan_t plan);
+
+/* Message of the last tomo_plan failure in this thread. */
+const char* tomo_plan_error(void);
+
+/* Release the plan's device memory (synchronises its last stream). NULL is OK. */
+tomo_status tomo_destroy(tomo_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOMO_H */

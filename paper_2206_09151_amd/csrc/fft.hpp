@@ -1,0 +1,268 @@
+// Register DFT codelets and an LDS-staged 2D FFT for one workgroup on gfx950.
+//
+// The 2D transform of an M x M complex block (M = R1 * R2, R2 | R1) runs with
+// M * R2 threads.  Each 1D pass is a two-stage Cooley-Tukey split of the index
+//   k = r + R2*m  ->  X[s + R1*k2] = sum_r W_R2^(r k2) W_M^(r s) sum_m W_R1^(m s) x[r + R2 m]
+// stage 1: a radix-R1 DFT in registers per (line, r), then the twiddle W_M^(r s);
+// stage 2: radix-R2 DFTs over r, after one exchange through LDS.  Between the
+// column and the row pass the block is transposed through LDS.  Stage-1 thread
+// mapping keeps r uniform across a 64-lane wave (M >= 64), so twiddle loads are
+// scalar.  The last stage maps lanes so that consecutive lanes own consecutive
+// output columns of one row (coalesced stores).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace tomo {
+
+// ---------------------------------------------------------------- compile-time trig
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// sin/cos of 2*pi*num/den by Taylor series after folding the angle into [-pi, pi].
+constexpr double ce_sin_turn(long num, long den) {
+  long n = ((num % den) + den) % den;           // [0, den)
+  double x = 2.0 * kPi * double(n) / double(den);
+  if (x > kPi) x -= 2.0 * kPi;                  // [-pi, pi]
+  double term = x, sum = x;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / double((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ce_cos_turn(long num, long den) { return ce_sin_turn(num * 4 + den, den * 4); }
+
+template <int I, int N>
+struct StaticFor {
+  template <class F>
+  __device__ __forceinline__ static void run(F&& f) {
+    if constexpr (I < N) {
+      f(std::integral_constant<int, I>{});
+      StaticFor<I + 1, N>::run(f);
+    }
+  }
+};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (FWD) or +i (INV): the quarter turn of the transform's kernel
+template <bool INV>
+__device__ __forceinline__ float2 qturn(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// v * exp(sgn * i*2*pi*K/R), sgn = -1 forward, +1 inverse; exact for multiples of a quarter turn.
+template <int R, int K, bool INV>
+__device__ __forceinline__ float2 rot(float2 v) {
+  constexpr int k = ((K % R) + R) % R;
+  if constexpr (k == 0) {
+    return v;
+  } else if constexpr (4 * k == R) {
+    return qturn<INV>(v);
+  } else if constexpr (2 * k == R) {
+    return make_float2(-v.x, -v.y);
+  } else if constexpr (4 * k == 3 * R) {
+    return qturn<!INV>(v);
+  } else {
+    constexpr float c = float(ce_cos_turn(k, R));
+    constexpr float s = float(INV ? ce_sin_turn(k, R) : -ce_sin_turn(k, R));
+    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+  }
+}
+
+// ---------------------------------------------------------------- DFT codelets
+// In-place DFT of R registers, natural order in and out.
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<1, INV> {
+  __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  __device__ __forceinline__ static void run(float2* x) {
+    constexpr float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+    float2 t1 = cadd(x[1], x[2]);
+    float2 t2 = csub(x[1], x[2]);
+    float2 m = make_float2(x[0].x - 0.5f * t1.x, x[0].y - 0.5f * t1.y);
+    float2 r = qturn<INV>(cscale(t2, h));  // -+ i * sin(2pi/3) * (x1 - x2)
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(m, r);
+    x[2] = csub(m, r);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    float2 c = cadd(x[1], x[3]), d = qturn<INV>(csub(x[1], x[3]));
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    x[1] = cadd(b, d);
+    x[3] = csub(b, d);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  __device__ __forceinline__ static void run(float2* x) {
+    constexpr float c1 = float(ce_cos_turn(1, 5)), c2 = float(ce_cos_turn(2, 5));
+    constexpr float s1 = float(ce_sin_turn(1, 5)), s2 = float(ce_sin_turn(2, 5));
+    float2 a1 = cadd(x[1], x[4]), a2 = cadd(x[2], x[3]);
+    float2 b1 = csub(x[1], x[4]), b2 = csub(x[2], x[3]);
+    float2 m1 = make_float2(x[0].x + c1 * a1.x + c2 * a2.x, x[0].y + c1 * a1.y + c2 * a2.y);
+    float2 m2 = make_float2(x[0].x + c2 * a1.x + c1 * a2.x, x[0].y + c2 * a1.y + c1 * a2.y);
+    // qturn applies the transform's sign of i
+    float2 n1 = qturn<INV>(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    float2 n2 = qturn<INV>(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    x[0] = make_float2(x[0].x + a1.x + a2.x, x[0].y + a1.y + a2.y);
+    x[1] = cadd(m1, n1);
+    x[4] = csub(m1, n1);
+    x[2] = cadd(m2, n2);
+    x[3] = csub(m2, n2);
+  }
+};
+
+constexpr int first_factor(int r) {
+  return (r % 4 == 0 && r != 4) ? 4 : (r % 2 == 0 ? 2 : (r % 3 == 0 ? 3 : (r % 5 == 0 ? 5 : r)));
+}
+
+// Composite R = A * B:  n = a + A b,  k = kb + B ka.
+template <int R, bool INV>
+struct Dft {
+  static constexpr int A = first_factor(R);
+  static constexpr int B = R / A;
+  static_assert(A * B == R && A > 1 && B > 1, "only 2,3,5-smooth radices");
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 t[R];
+    StaticFor<0, A>::run([&](auto ca) {
+      constexpr int a = decltype(ca)::value;
+      float2 s[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) s[b] = x[a + A * b];
+      Dft<B, INV>::run(s);
+      StaticFor<0, B>::run([&](auto ckb) {
+        constexpr int kb = decltype(ckb)::value;
+        t[a * B + kb] = rot<R, a * kb, INV>(s[kb]);
+      });
+    });
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) {
+      float2 s[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) s[a] = t[a * B + kb];
+      Dft<A, INV>::run(s);
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[kb + B * ka] = s[ka];
+    }
+  }
+};
+
+// ---------------------------------------------------------------- 2D FFT in LDS
+// Thread mapping (t = threadIdx.x, T = M*R2 threads):
+//   column stage 1: line = t % M (column kx), r = t / M; holds x[m] = Z[r + R2 m][line]
+//   row stage 2 output: sg = t % R2, y = t / R2; holds out[e*R2 + k2] =
+//       b[y][sg*(R1/R2) + e + R1*k2]     (e < R1/R2, k2 < R2)
+template <int M_, int R1_, int R2_>
+struct Fft2Shape {
+  static constexpr int M = M_, R1 = R1_, R2 = R2_;
+  static constexpr int T = M * R2;
+  static constexpr int E = R1 / R2;           // stage-2 DFTs per thread
+  static constexpr int TP = M + 1;            // transpose pitch (float2)
+  static constexpr int SP = R2 * M + 2;       // exchange pitch per stage-1 output index s
+  static constexpr int LDS_ELEMS = (M * TP > R1 * SP) ? M * TP : R1 * SP;
+  static constexpr size_t LDS_BYTES = size_t(LDS_ELEMS) * sizeof(float2);
+  static_assert(R1 * R2 == M && R1 % R2 == 0, "M = R1*R2 with R2 | R1");
+  static_assert(T <= 1024, "at most 1024 threads");
+};
+
+// Twiddle table tw[k] = exp(sgn i 2 pi k / M), FP64-rounded; index (r*s) mod M.
+template <class S, bool INV>
+__device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restrict__ lds,
+                                           const float2* __restrict__ tw) {
+  constexpr int M = S::M, R1 = S::R1, R2 = S::R2, E = S::E, TP = S::TP, SP = S::SP;
+  const int t = threadIdx.x;
+  const int line = t % M;
+  // r is uniform across a wave when M is a multiple of the wave size: say so, so
+  // that the twiddle loads below become scalar loads
+  int r_;
+  if constexpr (M % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / M);
+  else r_ = t / M;
+  const int r = r_;
+
+  // ---- column pass, stage 1 (radix R1 over m), twiddle W_M^(r s)
+  Dft<R1, INV>::run(x);
+#pragma unroll
+  for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
+#pragma unroll
+  for (int s = 0; s < R1; ++s) lds[s * SP + r * M + line] = x[s];
+  __syncthreads();
+  // ---- column pass, stage 2 (radix R2 over r) for s = sg*E + e, sg = t / M
+  {
+    const int sg = t / M;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = sg * E + e;
+      float2 y[R2];
+#pragma unroll
+      for (int rr = 0; rr < R2; ++rr) y[rr] = lds[s * SP + rr * M + line];
+      Dft<R2, INV>::run(y);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) x[e * R2 + k2] = y[k2];
+    }
+    __syncthreads();
+    // transpose: element (row Y = s + R1*k2, column = line)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = sg * E + e;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) lds[(s + R1 * k2) * TP + line] = x[e * R2 + k2];
+    }
+  }
+  __syncthreads();
+  // ---- row pass, stage 1: thread (row = line, r) reads columns r + R2*m
+#pragma unroll
+  for (int m = 0; m < R1; ++m) x[m] = lds[line * TP + r + R2 * m];
+  __syncthreads();
+  Dft<R1, INV>::run(x);
+#pragma unroll
+  for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
+#pragma unroll
+  for (int s = 0; s < R1; ++s) lds[s * SP + r * M + line] = x[s];
+  __syncthreads();
+  // ---- row pass, stage 2: thread (sg = t % R2, y = t / R2)
+  {
+    const int sg = t % R2;
+    const int y = t / R2;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = sg * E + e;
+      float2 v[R2];
+#pragma unroll
+      for (int rr = 0; rr < R2; ++rr) v[rr] = lds[s * SP + rr * M + y];
+      Dft<R2, INV>::run(v);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) x[e * R2 + k2] = v[k2];
+    }
+  }
+}
+
+}  // namespace tomo

@@ -1,0 +1,553 @@
+// C-ABI host side of libtomo.so: validation, view frames, plan tables, workspace,
+// batching and error reporting.  Every compute step runs in the kernels of
+// tomo_kernels.hip; the host only prepares geometry constants (frames, angular
+// weights, propagator and twiddle tables) in FP64 at plan time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/tomo.h"
+#include "tomo_internal.hpp"
+
+using tomo::ViewGeom;
+
+struct tomo_plan_s {
+  tomo_params p{};
+  int N = 0, M = 0, K = 0, n = 0, npairs = 0, batch = 0;
+  bool axis_fast = false;
+  ViewGeom* d_geom = nullptr;   // [n]
+  float4* d_filt = nullptr;     // [n][M][M]
+  float2* d_prop = nullptr;     // [npairs][M]
+  float2* d_tw_fwd = nullptr;   // [M]
+  float2* d_tw_inv = nullptr;   // [M]
+  float4* d_q = nullptr;        // [n][M][M]  filtered spectra of every view
+  float* d_stack = nullptr;     // [batch][M][K][M]
+  int* d_status = nullptr;
+  std::string err;
+  // tracing: events around launches while timing is on
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> recs;
+  double tot_ms[3] = {0, 0, 0};
+  long long launches[3] = {0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_plan_error;
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+struct Resolved {
+  int N, M, K, n, npairs, batch;
+  size_t table_bytes, work_bytes;
+};
+
+size_t stack_view_bytes(int M, int K) { return size_t(M) * K * M * sizeof(float); }
+
+// Resolve defaults and sizes; returns an error message or "" and fills r.
+std::string resolve(const tomo_params* p, Resolved* r) {
+  if (!p) return "params is NULL";
+  if (p->n_vox < 2 || p->n_vox > 1024) return "n_vox must be in [2, 1024]";
+  if (p->n_angles < 1) return "n_angles must be >= 1";
+  if (!(p->voxel_size > 0) || !std::isfinite(p->voxel_size)) return "voxel_size must be finite and > 0";
+  if (!(p->wavelength > 0) || !std::isfinite(p->wavelength)) return "wavelength must be finite and > 0";
+  if (!std::isfinite(p->sigma)) return "sigma must be finite";
+  if (!(p->epsilon > 0) || !std::isfinite(p->epsilon)) return "epsilon must be finite and > 0";
+  if (p->eps_sampling < 0 || !std::isfinite(p->eps_sampling)) return "eps_sampling must be finite and >= 0";
+  if (p->i_in < 0 || !std::isfinite(p->i_in)) return "i_in must be finite and >= 0";
+  if (p->ewald != 0 && p->ewald != 1) return "ewald must be 0 or 1";
+  if (p->weight_mode < 0 || p->weight_mode > 2) return "weight_mode must be 0, 1 or 2";
+  if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
+  if (p->angle_batch < 0) return "angle_batch must be >= 0";
+  r->N = p->n_vox;
+  r->M = p->n_pix ? p->n_pix : p->n_vox;
+  if (p->n_pix < 0) return "n_pix must be >= 0";
+  if (p->n_planes < 0) return "n_planes must be >= 0";
+  r->K = p->ewald ? (p->n_planes ? p->n_planes : p->n_vox) : 1;
+  if (r->K > 2 * r->N) return "n_planes must be <= 2 * n_vox";
+  r->n = p->n_angles;
+  r->npairs = (r->K + 1) / 2;
+  const size_t sv = stack_view_bytes(r->M, r->K);
+  const size_t qv = size_t(r->M) * r->M * sizeof(float4);
+  if (p->angle_batch > 0) {
+    r->batch = std::min(p->angle_batch, r->n);
+  } else {
+    // automatic: about 128 MiB of stacks per batch (they stay in the 256 MB last-level
+    // cache between the back-propagation and the gridding kernels), a multiple of 8
+    const size_t target = size_t(128) << 20;
+    int b = int(std::max<size_t>(1, target / sv));
+    if (b >= 8) b -= b % 8;
+    r->batch = std::min(b, r->n);
+  }
+  r->table_bytes = size_t(r->n) * sizeof(ViewGeom) + size_t(r->n) * qv + size_t(r->npairs) * r->M * 8 +
+                   2 * size_t(r->M) * 8 + 256;
+  r->work_bytes = size_t(r->n) * qv + size_t(r->batch) * sv;
+  return "";
+}
+
+std::string supported(const tomo_params* p, const Resolved& r) {
+  if (p->plane_dtype != TOMO_F32) return "only TOMO_F32 plane storage is implemented";
+  if (!tomo::fft_supported(r.M)) {
+    char b[160];
+    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128)", r.M);
+    return b;
+  }
+  return "";
+}
+
+// O1-style frames in FP64: v = y projected on the detector plane (x near the poles), u = v x d.
+void make_frames(const double* dirs, const double* vaxes, int n, std::vector<ViewGeom>& g) {
+  g.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const double* d = dirs + 3 * i;
+    double ref[3];
+    if (vaxes) {
+      std::memcpy(ref, vaxes + 3 * i, sizeof ref);
+    } else {
+      // |y x d| = sqrt(d_x^2 + d_z^2)
+      const double cr = std::sqrt(d[0] * d[0] + d[2] * d[2]);
+      ref[0] = cr < 1e-6 ? 1.0 : 0.0;
+      ref[1] = cr < 1e-6 ? 0.0 : 1.0;
+      ref[2] = 0.0;
+    }
+    const double dot = ref[0] * d[0] + ref[1] * d[1] + ref[2] * d[2];
+    double v[3] = {ref[0] - dot * d[0], ref[1] - dot * d[1], ref[2] - dot * d[2]};
+    const double nv = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (double& x : v) x /= nv;
+    ViewGeom& vg = g[i];
+    for (int a = 0; a < 3; ++a) {
+      vg.d[a] = d[a];
+      vg.v[a] = v[a];
+    }
+    vg.u[0] = v[1] * d[2] - v[2] * d[1];
+    vg.u[1] = v[2] * d[0] - v[0] * d[2];
+    vg.u[2] = v[0] * d[1] - v[1] * d[0];
+    vg.R = 0;
+    vg.a = 0;
+    vg.pad = 0;
+  }
+}
+
+// Trapezoid weights of the view angles folded into [0, pi) on a circle of period pi.
+void axis_weights(const double* dirs, int n, std::vector<ViewGeom>& g) {
+  std::vector<double> phi(n);
+  for (int i = 0; i < n; ++i) {
+    double a = std::atan2(dirs[3 * i], dirs[3 * i + 2]);
+    a = std::fmod(a, kPi);
+    if (a < 0) a += kPi;
+    if (a >= kPi) a -= kPi;
+    phi[i] = a;
+  }
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return phi[a] < phi[b]; });
+  for (int k = 0; k < n; ++k) {
+    const double nxt = (k + 1 < n) ? phi[order[k + 1]] : phi[order[0]] + kPi;
+    const double prv = (k > 0) ? phi[order[k - 1]] : phi[order[n - 1]] - kPi;
+    g[order[k]].a = 0.5 * (nxt - prv);
+  }
+}
+
+template <class T>
+hipError_t dev_alloc(T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
+}
+
+hipEvent_t take_event(tomo_plan_s* pl) {
+  if (!pl->pool.empty()) {
+    hipEvent_t e = pl->pool.back();
+    pl->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch wrapper: records an event pair around the launch when timing is on.
+template <class F>
+hipError_t timed(tomo_plan_s* pl, int kind, hipStream_t s, F&& launch) {
+  if (!pl->timing) return launch();
+  hipEvent_t a = take_event(pl), b = take_event(pl);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  pl->recs.push_back({kind, a, b});
+  return e;
+}
+
+void free_plan(tomo_plan_s* pl) {
+  for (auto& r : pl->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pl->pool) (void)hipEventDestroy(e);
+  pl->recs.clear();
+  pl->pool.clear();
+  (void)hipFree(pl->d_geom);
+  (void)hipFree(pl->d_filt);
+  (void)hipFree(pl->d_prop);
+  (void)hipFree(pl->d_tw_fwd);
+  (void)hipFree(pl->d_tw_inv);
+  (void)hipFree(pl->d_q);
+  (void)hipFree(pl->d_stack);
+  (void)hipFree(pl->d_status);
+}
+
+tomo_status fail(tomo_plan_s* pl, tomo_status st, const std::string& msg) {
+  if (pl) pl->err = msg;
+  return st;
+}
+
+tomo_status dev_fail(tomo_plan_s* pl, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  if (pl) pl->err = m;
+  return TOMO_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tomo_status_string(tomo_status s) {
+  switch (s) {
+    case TOMO_OK: return "ok";
+    case TOMO_EINVAL: return "invalid argument";
+    case TOMO_ENOMEM: return "out of device memory or workspace limit";
+    case TOMO_EDEVICE: return "device error";
+    case TOMO_EDOMAIN: return "image value <= 0 or not finite";
+    case TOMO_EUNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+const char* tomo_last_error(tomo_plan_t plan) { return plan ? plan->err.c_str() : "plan is NULL"; }
+
+const char* tomo_plan_error(void) { return g_plan_error.c_str(); }
+
+size_t tomo_workspace_bytes(const tomo_params* p) {
+  Resolved r{};
+  if (!resolve(p, &r).empty()) return 0;
+  return r.table_bytes + r.work_bytes;
+}
+
+int32_t tomo_batch_capacity(tomo_plan_t plan) { return plan ? plan->batch : 0; }
+
+size_t tomo_stack_bytes(tomo_plan_t plan, int32_t nb) {
+  if (!plan || nb < 0) return 0;
+  return size_t(nb) * stack_view_bytes(plan->M, plan->K);
+}
+
+tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* vaxes, const double* dist,
+                      void* stream, tomo_plan_t* out) {
+  g_plan_error.clear();
+  auto perr = [](tomo_status st, const std::string& m) {
+    g_plan_error = m;
+    return st;
+  };
+  if (!out) return perr(TOMO_EINVAL, "out is NULL");
+  if (!dirs) return perr(TOMO_EINVAL, "dirs is NULL");
+  if (!dist) return perr(TOMO_EINVAL, "dist is NULL");
+  Resolved r{};
+  std::string m = resolve(p, &r);
+  if (!m.empty()) return perr(TOMO_EINVAL, m);
+  m = supported(p, r);
+  if (!m.empty()) return perr(TOMO_EUNSUPPORTED, m);
+  for (int i = 0; i < r.n; ++i) {
+    const double* d = dirs + 3 * i;
+    const double nn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!std::isfinite(nn) || std::fabs(nn - 1.0) > 1e-9) {
+      char b[96];
+      std::snprintf(b, sizeof b, "direction %d is not a unit vector (norm %.17g)", i, nn);
+      return perr(TOMO_EINVAL, b);
+    }
+    if (!std::isfinite(dist[i])) return perr(TOMO_EINVAL, "dist must be finite");
+    if (p->weight_mode == TOMO_RAMP_AXIS && std::fabs(d[1]) > 1e-9)
+      return perr(TOMO_EINVAL, "TOMO_RAMP_AXIS needs every direction perpendicular to the y axis");
+    if (vaxes) {
+      const double* va = vaxes + 3 * i;
+      const double dot = va[0] * d[0] + va[1] * d[1] + va[2] * d[2];
+      const double px = va[0] - dot * d[0], py = va[1] - dot * d[1], pz = va[2] - dot * d[2];
+      if (!(std::sqrt(px * px + py * py + pz * pz) > 1e-9))
+        return perr(TOMO_EINVAL, "vaxes must have a component perpendicular to its direction");
+    }
+  }
+  const size_t total = r.table_bytes + r.work_bytes;
+  if (p->max_workspace_bytes && total > p->max_workspace_bytes) {
+    char b[128];
+    std::snprintf(b, sizeof b, "plan needs %zu bytes > max_workspace_bytes %zu", total, p->max_workspace_bytes);
+    return perr(TOMO_ENOMEM, b);
+  }
+
+  auto* pl = new tomo_plan_s();
+  pl->p = *p;
+  pl->N = r.N;
+  pl->M = r.M;
+  pl->K = r.K;
+  pl->n = r.n;
+  pl->npairs = r.npairs;
+  pl->batch = r.batch;
+  pl->p.n_pix = r.M;
+  pl->p.n_planes = r.K;
+  if (pl->p.i_in == 0) pl->p.i_in = 1.0;
+  if (pl->p.eps_sampling == 0) pl->p.eps_sampling = 1e-3;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  std::vector<ViewGeom> geo;
+  make_frames(dirs, vaxes, r.n, geo);
+  for (int i = 0; i < r.n; ++i) geo[i].R = dist[i];
+  if (p->weight_mode == TOMO_RAMP_AXIS) axis_weights(dirs, r.n, geo);
+  // Single-axis gather path: every v is exactly the y axis and u, d lie in the xz plane,
+  // and detector rows line up with voxel rows (M - N even).
+  bool axis = ((r.M - r.N) % 2 == 0);
+  for (int i = 0; i < r.n && axis; ++i)
+    axis = geo[i].v[0] == 0.0 && geo[i].v[1] == 1.0 && geo[i].v[2] == 0.0 && geo[i].u[1] == 0.0 &&
+           geo[i].d[1] == 0.0;
+  pl->axis_fast = axis;
+
+  // propagator table: (cos, sin)(pi lambda z'_p q^2), z'_p = (p - (K-1)/2) dx; twiddles
+  std::vector<float2> prop(size_t(r.npairs) * r.M), twf(r.M), twi(r.M);
+  for (int pp = 0; pp < r.npairs; ++pp) {
+    const double z = (pp - 0.5 * (r.K - 1)) * p->voxel_size;
+    for (int k = 0; k < r.M; ++k) {
+      const int ks = (k < (r.M + 1) / 2) ? k : k - r.M;
+      const double q = ks / (double(r.M) * p->voxel_size);
+      const double ph = kPi * p->wavelength * z * q * q;
+      prop[size_t(pp) * r.M + k] = make_float2(float(std::cos(ph)), float(std::sin(ph)));
+    }
+  }
+  for (int k = 0; k < r.M; ++k) {
+    const double a = 2.0 * kPi * k / r.M;
+    twf[k] = make_float2(float(std::cos(a)), float(-std::sin(a)));
+    twi[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+
+  hipError_t e = hipSuccess;
+  const size_t mm = size_t(r.M) * r.M;
+  if ((e = dev_alloc(&pl->d_geom, size_t(r.n))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_filt, mm * r.n)) != hipSuccess ||
+      (e = dev_alloc(&pl->d_prop, prop.size())) != hipSuccess ||
+      (e = dev_alloc(&pl->d_tw_fwd, size_t(r.M))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_tw_inv, size_t(r.M))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_q, mm * r.n)) != hipSuccess ||
+      (e = dev_alloc(&pl->d_stack, size_t(r.batch) * r.M * r.K * r.M)) != hipSuccess ||
+      (e = dev_alloc(&pl->d_status, size_t(1))) != hipSuccess) {
+    free_plan(pl);
+    delete pl;
+    (void)hipGetLastError();
+    return perr(e == hipErrorOutOfMemory ? TOMO_ENOMEM : TOMO_EDEVICE,
+                std::string("allocation failed: ") + hipGetErrorString(e));
+  }
+  double* d_wtab = nullptr;
+  unsigned long long* d_smat = nullptr;
+  auto cleanup_fail = [&](hipError_t err, const char* where) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(d_wtab);
+    (void)hipFree(d_smat);
+    free_plan(pl);
+    delete pl;
+    (void)hipGetLastError();
+    return perr(err == hipErrorOutOfMemory ? TOMO_ENOMEM : TOMO_EDEVICE,
+                std::string(where) + ": " + hipGetErrorString(err));
+  };
+  if ((e = hipMemcpyAsync(pl->d_geom, geo.data(), sizeof(ViewGeom) * r.n, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(pl->d_prop, prop.data(), sizeof(float2) * prop.size(), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(pl->d_tw_fwd, twf.data(), sizeof(float2) * r.M, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(pl->d_tw_inv, twi.data(), sizeof(float2) * r.M, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemsetAsync(pl->d_status, 0, sizeof(int), s)))
+    return cleanup_fail(e, "upload");
+
+  tomo::FilterArgs fa{};
+  fa.n_views = r.n;
+  fa.M = r.M;
+  fa.N = r.N;
+  fa.dx = p->voxel_size;
+  fa.lambda = p->wavelength;
+  fa.sigma = p->sigma;
+  fa.epsilon = p->epsilon;
+  fa.eps_sampling = pl->p.eps_sampling;
+  fa.ewald = p->ewald;
+  fa.mode = p->weight_mode;
+  if (p->weight_mode == TOMO_SAMPLING) {
+    const size_t n3 = size_t(r.N) * r.N * r.N;
+    if ((e = dev_alloc(&d_smat, n3)) != hipSuccess || (e = dev_alloc(&d_wtab, mm * r.n)) != hipSuccess)
+      return cleanup_fail(e, "sampling-matrix allocation");
+    if ((e = hipMemsetAsync(d_smat, 0, n3 * sizeof(unsigned long long), s)) != hipSuccess)
+      return cleanup_fail(e, "sampling-matrix clear");
+    if ((e = tomo::launch_sampling(fa, pl->d_geom, d_smat, d_wtab, s)) != hipSuccess)
+      return cleanup_fail(e, "sampling-matrix kernels");
+  }
+  if ((e = tomo::launch_filter_table(fa, pl->d_geom, d_wtab, pl->d_filt, s)) != hipSuccess)
+    return cleanup_fail(e, "filter-table kernel");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup_fail(e, "plan synchronise");
+  (void)hipFree(d_wtab);
+  (void)hipFree(d_smat);
+  *out = pl;
+  return TOMO_OK;
+}
+
+tomo_status tomo_destroy(tomo_plan_t plan) {
+  if (!plan) return TOMO_OK;
+  (void)hipDeviceSynchronize();
+  free_plan(plan);
+  delete plan;
+  return TOMO_OK;
+}
+
+static tomo_status check_range(tomo_plan_t pl, int32_t first, int32_t nb) {
+  if (first < 0 || nb < 0 || first > pl->n || nb > pl->n - first)
+    return fail(pl, TOMO_EINVAL, "view range [first, first+nb) outside [0, n_angles)");
+  return TOMO_OK;
+}
+
+// Spectra of views [first, first+nb) into the plan's per-view slots of d_q.
+static tomo_status run_spectra(tomo_plan_t pl, const float* d_images, int32_t first, int32_t nb, hipStream_t s) {
+  const size_t mm = size_t(pl->M) * pl->M;
+  hipError_t e = timed(pl, 0, s, [&] {
+    return tomo::launch_spectra(pl->M, d_images, pl->d_filt + size_t(first) * mm, pl->d_tw_fwd,
+                                pl->d_q + size_t(first) * mm, pl->d_status, 1.0 / pl->p.i_in, nb, s);
+  });
+  if (e != hipSuccess) return dev_fail(pl, e, "spectra kernel");
+  return TOMO_OK;
+}
+
+tomo_status tomo_backpropagate(tomo_plan_t pl, const float* d_images, int32_t first, int32_t nb, void* d_planes,
+                               void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (nb == 0) return TOMO_OK;
+  if (!d_images || !d_planes) return fail(pl, TOMO_EINVAL, "null device pointer");
+  tomo_status st = check_range(pl, first, nb);
+  if (st != TOMO_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = run_spectra(pl, d_images, first, nb, s)) != TOMO_OK) return st;
+  const size_t mm = size_t(pl->M) * pl->M;
+  hipError_t e = timed(pl, 1, s, [&] {
+    return tomo::launch_planes(pl->M, pl->d_q + size_t(first) * mm, pl->d_prop, pl->d_tw_inv,
+                               static_cast<float*>(d_planes), pl->K, pl->npairs, nb, s);
+  });
+  if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
+  return TOMO_OK;
+}
+
+tomo_status tomo_grid(tomo_plan_t pl, const void* d_planes, int32_t first, int32_t nb, float* d_volume,
+                      void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (nb == 0) return TOMO_OK;
+  if (!d_planes || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
+  if (first < 0 || nb < 0 || first > pl->n || nb > pl->n - first)
+    return fail(pl, TOMO_EINVAL, "view range [first, first+nb) outside [0, n_angles)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = timed(pl, 2, s, [&] {
+    return tomo::launch_grid(pl->axis_fast, static_cast<const float*>(d_planes), pl->d_geom + first, d_volume,
+                             pl->N, pl->M, pl->K, nb, 1, pl->p.ewald ? 0 : 1, s);
+  });
+  if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
+  return TOMO_OK;
+}
+
+tomo_status tomo_sync(tomo_plan_t pl, void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(pl, e, "synchronise");
+  int flag = 0;
+  if ((e = hipMemcpy(&flag, pl->d_status, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return dev_fail(pl, e, "status read");
+  if (flag) {
+    const int zero = 0;
+    if ((e = hipMemcpy(pl->d_status, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return dev_fail(pl, e, "status reset");
+    return fail(pl, TOMO_EDOMAIN, "an image value was <= 0 or not finite");
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_volume, void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (!d_images || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t mm = size_t(pl->M) * pl->M;
+  // spectra of all views in one launch (one workgroup per view), then per batch the
+  // depth planes and the gridding
+  tomo_status st = run_spectra(pl, d_images, 0, pl->n, s);
+  if (st != TOMO_OK) return st;
+  for (int first = 0; first < pl->n; first += pl->batch) {
+    const int nb = std::min(pl->batch, pl->n - first);
+    hipError_t e = timed(pl, 1, s, [&] {
+      return tomo::launch_planes(pl->M, pl->d_q + size_t(first) * mm, pl->d_prop, pl->d_tw_inv, pl->d_stack,
+                                 pl->K, pl->npairs, nb, s);
+    });
+    if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
+    e = timed(pl, 2, s, [&] {
+      return tomo::launch_grid(pl->axis_fast, pl->d_stack, pl->d_geom + first, d_volume, pl->N, pl->M, pl->K,
+                               nb, first > 0 ? 1 : 0, pl->p.ewald ? 0 : 1, s);
+    });
+    if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
+  }
+  return tomo_sync(pl, stream);
+}
+
+tomo_status tomo_timing_enable(tomo_plan_t pl, int32_t enable) {
+  if (!pl) return TOMO_EINVAL;
+  pl->timing = enable != 0;
+  return TOMO_OK;
+}
+
+tomo_status tomo_timing_read(tomo_plan_t pl, double* total_ms, int64_t* launches, int32_t reset) {
+  if (!pl || !total_ms || !launches) return TOMO_EINVAL;
+  for (auto& r : pl->recs) {
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return dev_fail(pl, e, "timing events");
+    pl->tot_ms[r.kind] += ms;
+    pl->launches[r.kind] += 1;
+    pl->pool.push_back(r.a);
+    pl->pool.push_back(r.b);
+  }
+  pl->recs.clear();
+  for (int k = 0; k < 3; ++k) {
+    total_ms[k] = pl->tot_ms[k];
+    launches[k] = pl->launches[k];
+    if (reset) {
+      pl->tot_ms[k] = 0;
+      pl->launches[k] = 0;
+    }
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_filtered_spectra(tomo_plan_t pl, const float* d_images, int32_t first, int32_t nb, float* d_out,
+                                  void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (nb == 0) return TOMO_OK;
+  if (!d_images || !d_out) return fail(pl, TOMO_EINVAL, "null device pointer");
+  tomo_status st = check_range(pl, first, nb);
+  if (st != TOMO_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = run_spectra(pl, d_images, first, nb, s)) != TOMO_OK) return st;
+  hipError_t e = tomo::launch_spectra_out(pl->d_q + size_t(first) * size_t(pl->M) * pl->M,
+                                          reinterpret_cast<float2*>(d_out), pl->M, nb, s);
+  if (e != hipSuccess) return dev_fail(pl, e, "spectra output kernel");
+  return TOMO_OK;
+}
+
+}  // extern "C"

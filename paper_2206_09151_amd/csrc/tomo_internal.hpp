@@ -1,0 +1,44 @@
+// Internal interface between the C-ABI host code and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tomo {
+
+// Per-view geometry in FP64: detector frame (u, v, d), distance R_n and the
+// angular quadrature weight a_n of the axis ramp.
+struct ViewGeom {
+  double u[3], v[3], d[3];
+  double R, a, pad;
+};
+
+struct FilterArgs {
+  int n_views, M, N;
+  double dx, lambda, sigma, epsilon, eps_sampling;
+  int ewald, mode;  // mode: 0 axis ramp, 1 isotropic ramp, 2 sampling matrix
+};
+
+// Supported detector sizes of the LDS-resident 2D FFT.
+bool fft_supported(int M);
+int fft_threads(int M);
+
+// g = ln(I/I_in) -> 2D DFT -> (G1 G, G2 G) for nb views.  filt, q: [nb][M][M] float4.
+hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
+                          float4* q, int* status, double inv_iin, int nb, hipStream_t s);
+// Plane pairs (p, K-1-p), p < npairs, of nb views -> stack [nb][M][K][M].
+hipError_t launch_planes(int M, const float4* q, const float2* prop, const float2* tw_inv,
+                         float* stack, int K, int npairs, int nb, hipStream_t s);
+// Trilinear gather of nb stacks into V[N][N][N] (accumulate: V += ..., else V = ...).
+// flat: one plane without depth axis (no Ewald curvature): bilinear in the detector plane.
+hipError_t launch_grid(bool axis_fast, const float* stack, const ViewGeom* geom, float* vol, int N,
+                       int M, int K, int nb, int accumulate, int flat, hipStream_t s);
+// Plan-time tables.
+hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const double* wtab,
+                               float4* filt, hipStream_t s);
+hipError_t launch_sampling(const FilterArgs& fa, const ViewGeom* geom, unsigned long long* smat,
+                           double* wtab, hipStream_t s);
+hipError_t launch_spectra_out(const float4* q, float2* out, int M, int nb, hipStream_t s);
+
+}  // namespace tomo

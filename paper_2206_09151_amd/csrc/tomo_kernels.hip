@@ -1,0 +1,561 @@
+// gfx950 kernels of the reconstruction hot path.
+//
+//   k_spectra   per view: g = ln(I/I_in) (eq. 4 left side), 2D DFT (F2 of Section 2,
+//               kernel exp(-i 2 pi r.q)), multiplied by the plan's filter table so
+//               that the Hermitian split needed below is ready:
+//                 Q1 = (1+i) F_h G / M^2,   Q2 = -(1+i) F_a G / M^2,
+//               F = C W H (eq. 11), F_h / F_a its Hermitian / anti-Hermitian parts.
+//   k_planes    per view and plane pair (j, K-1-j): the planes' spectra are
+//               Y_j = Herm[F e^{-i phi_j} G], phi_j = pi lambda z'_j q^2 (eq. 3 on the
+//               paraboloid of eqs. 8/10).  Since z'_{K-1-j} = -z'_j,
+//                 Y_j + i Y_{K-1-j} = cos(phi_j) Q1 + sin(phi_j) Q2,
+//               and one complex inverse 2D FFT yields plane j (real part) and plane
+//               K-1-j (imaginary part).  Writes the stack [view][row][plane][col].
+//   k_grid_*    trilinear gather of the stacks at every voxel's view-frame position
+//               (text after eq. 11), summed over the batch's views in ascending
+//               order in registers, then one read-modify-write of V (no atomics).
+//   k_filter_table, k_sampling_*: plan-time tables in FP64, stored FP32.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.hpp"
+#include "tomo_internal.hpp"
+
+namespace tomo {
+
+// ------------------------------------------------------------------ FFT shapes
+template <int M>
+struct Shape;
+template <> struct Shape<16> : Fft2Shape<16, 4, 4> {};
+template <> struct Shape<32> : Fft2Shape<32, 8, 4> {};
+template <> struct Shape<48> : Fft2Shape<48, 12, 4> {};
+template <> struct Shape<64> : Fft2Shape<64, 16, 4> {};
+template <> struct Shape<80> : Fft2Shape<80, 20, 4> {};
+template <> struct Shape<96> : Fft2Shape<96, 24, 4> {};
+template <> struct Shape<128> : Fft2Shape<128, 16, 8> {};
+
+bool fft_supported(int M) {
+  switch (M) {
+    case 16: case 32: case 48: case 64: case 80: case 96: case 128: return true;
+    default: return false;
+  }
+}
+
+int fft_threads(int M) {
+  switch (M) {
+    case 16: return Shape<16>::T;
+    case 32: return Shape<32>::T;
+    case 48: return Shape<48>::T;
+    case 64: return Shape<64>::T;
+    case 80: return Shape<80>::T;
+    case 96: return Shape<96>::T;
+    case 128: return Shape<128>::T;
+    default: return 0;
+  }
+}
+
+// ------------------------------------------------------------------ K1: spectra
+template <int M>
+__global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict__ images,
+                                                         const float4* __restrict__ filt,
+                                                         const float2* __restrict__ tw_fwd,
+                                                         float4* __restrict__ q, int* __restrict__ status,
+                                                         double inv_iin) {
+  using S = Shape<M>;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  const int t = threadIdx.x;
+  const int view = blockIdx.x;
+  const int line = t % M, r = t / M;
+  const float* img = images + size_t(view) * M * M;
+  float2 x[S::R1];
+  int bad = 0;
+#pragma unroll
+  for (int m = 0; m < S::R1; ++m) {
+    const float iv = img[(r + S::R2 * m) * M + line];
+    const bool ok = (iv > 0.0f) && (iv < INFINITY);
+    bad |= !ok;
+    // contrast in FP64, rounded once: ln(I/I_in) of an FP32 intensity near I_in
+    const double g = ok ? log(double(iv) * inv_iin) : 0.0;
+    x[m] = make_float2(float(g), 0.0f);
+  }
+  if (bad) atomicOr(status, 1);
+  fft2_block<S, false>(x, lds, tw_fwd);
+  const int sg = t % S::R2, ky = t / S::R2;
+  const size_t row = (size_t(view) * M + ky) * M;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) {
+#pragma unroll
+    for (int k2 = 0; k2 < S::R2; ++k2) {
+      const int kx = sg * S::E + e + S::R1 * k2;
+      const float4 f = filt[row + kx];
+      const float2 gg = x[e * S::R2 + k2];
+      float4 o;
+      o.x = f.x * gg.x - f.y * gg.y;
+      o.y = f.x * gg.y + f.y * gg.x;
+      o.z = f.z * gg.x - f.w * gg.y;
+      o.w = f.z * gg.y + f.w * gg.x;
+      q[row + kx] = o;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ K3: planes
+// Workgroup -> (view, pair) mapping keeps all pairs of one view on one XCD
+// (workgroups are dealt to the 8 XCDs round robin), so the view's Q block is
+// fetched into one L2 only.
+template <int M>
+__global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict__ q,
+                                                        const float2* __restrict__ prop,
+                                                        const float2* __restrict__ tw_inv,
+                                                        float* __restrict__ stack, int K, int npairs,
+                                                        int nb) {
+  using S = Shape<M>;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  const int wg = blockIdx.x;
+  const int xcd = wg & 7, k = wg >> 3;
+  const int view = xcd + 8 * (k / npairs);
+  const int p = k % npairs;
+  if (view >= nb) return;  // whole workgroup leaves together: no barrier is skipped by part of it
+  const int t = threadIdx.x;
+  const int line = t % M;
+  int r_;
+  if constexpr (M % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / M);
+  else r_ = t / M;
+  const int r = r_;
+  const float4* qv = q + size_t(view) * M * M;
+  const float2* pr = prop + size_t(p) * M;
+  const float2 cx = pr[line];
+  float2 x[S::R1];
+#pragma unroll
+  for (int m = 0; m < S::R1; ++m) {
+    const int ky = r + S::R2 * m;
+    const float2 cy = pr[ky];
+    const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+    const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+    const float4 qq = qv[ky * M + line];
+    x[m] = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
+  }
+  fft2_block<S, true>(x, lds, tw_inv);
+  const int sg = t % S::R2, y = t / S::R2;
+  const int pa = p, pb = K - 1 - p;
+  float* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
+  float* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
+#pragma unroll
+  for (int k2 = 0; k2 < S::R2; ++k2) {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) {
+      const int xc = sg * S::E + e + S::R1 * k2;
+      rowa[xc] = x[e * S::R2 + k2].x;
+    }
+  }
+  if (pb != pa) {
+#pragma unroll
+    for (int k2 = 0; k2 < S::R2; ++k2) {
+#pragma unroll
+      for (int e = 0; e < S::E; ++e) {
+        const int xc = sg * S::E + e + S::R1 * k2;
+        rowb[xc] = x[e * S::R2 + k2].y;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ inspection
+__global__ void k_spectra_out(const float4* __restrict__ q, float2* __restrict__ out, size_t count,
+                              float m2) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float4 v = q[i];
+  // F G = M^2 (Q1 - Q2) / (1 + i),  1/(1+i) = (1 - i)/2
+  const float a = v.x - v.z, b = v.y - v.w;
+  out[i] = make_float2(0.5f * m2 * (a + b), 0.5f * m2 * (b - a));
+}
+
+// ------------------------------------------------------------------ K4: gridding
+constexpr int GT = 16;  // voxel tile edge (x) x (z or y) per 256-thread workgroup
+
+// Single-axis views (v = y exactly, M - N even): the detector row of voxel row iy is
+// iy + (M-N)/2 exactly, so the trilinear weights reduce to bilinear ones in
+// (plane, col), shared by the YB voxel rows of a thread.
+//
+// Per view, the workgroup's 16 x 16 (x, z) tile maps into a rotated square of the
+// (plane, col) grid.  Its bounding box (at most 24 x 24 for a 16 x 16 tile; the
+// column start is rounded down to a multiple of 4 for 16-byte loads) is staged into
+// LDS for the YB rows with coalesced vector loads, zero outside the stack, so the
+// bilinear taps are plain LDS reads with no bounds masks.
+constexpr int AX_BOXH = 24;     // planes staged per row
+constexpr int AX_BOXW = 28;     // columns staged per row (24 + alignment slack), 7 float4
+constexpr int AX_BOXP = 29;     // LDS pitch (odd: spreads the rows over the banks)
+
+template <int YB>
+__global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ stack,
+                                                   const ViewGeom* __restrict__ geom,
+                                                   float* __restrict__ vol, int N, int M, int K,
+                                                   int nb, int accumulate, int flat) {
+  __shared__ float box[YB][AX_BOXH][AX_BOXP];
+  // Workgroups are dealt to the 8 XCDs round robin: give every tile of one voxel-row
+  // block to the same XCD, so each detector row of the stacks is fetched into one L2.
+  const int ntx = (N + GT - 1) / GT;
+  const int tiles = ntx * ntx;                          // (x, z) tiles per row block
+  const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
+  const int yblk = xcd + 8 * (k / tiles), tile = k % tiles;
+  const int y0 = yblk * YB;
+  if (y0 >= N) return;                                  // uniform: the whole workgroup leaves
+  const int tx0 = (tile % ntx) * GT, tz0 = (tile / ntx) * GT;
+  const int ix = tx0 + (threadIdx.x % GT);
+  const int iz = tz0 + (threadIdx.x / GT);
+  const bool live = ix < N && iz < N;                   // ragged tiles: no store, but keep barriers
+  const double c = 0.5 * (N - 1);
+  const double rx = ix - c, rz = iz - c;
+  const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
+  const int rowoff = (M - N) / 2;
+  const size_t plane_sz = size_t(K) * M;                // floats per detector row of the stack
+  const bool vec4 = (M % 4) == 0;
+  float acc[YB];
+#pragma unroll
+  for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
+  for (int n = 0; n < nb; ++n) {
+    const ViewGeom& g = geom[n];
+    // box origin from the tile corners (uniform)
+    const double ax = tx0 - c, bx = tx0 + GT - 1 - c, az = tz0 - c, bz = tz0 + GT - 1 - c;
+    const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
+    const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
+    const int c0 = int(floor(cmin)) & ~3;               // 16-byte aligned column start
+    const int p0 = flat ? 0 : int(floor(pmin));
+    const float* vbase = stack + size_t(n) * plane_sz * M;
+    __syncthreads();                                    // previous view's reads are done
+    // stage [YB][BOXH][BOXW]: 7 float4 per (row, plane)
+    for (int e = threadIdx.x; e < YB * AX_BOXH * (AX_BOXW / 4); e += 256) {
+      const int q = e % (AX_BOXW / 4), pl = (e / (AX_BOXW / 4)) % AX_BOXH, j = e / ((AX_BOXW / 4) * AX_BOXH);
+      const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + 4 * q;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      const bool rok = (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K);
+      if (rok) {
+        const float* src = vbase + size_t(row) * plane_sz + size_t(pp) * M;
+        if (vec4 && cc >= 0 && cc + 3 < M) {
+          v = *reinterpret_cast<const float4*>(src + cc);
+        } else {
+          v.x = unsigned(cc) < unsigned(M) ? src[cc] : 0.f;
+          v.y = unsigned(cc + 1) < unsigned(M) ? src[cc + 1] : 0.f;
+          v.z = unsigned(cc + 2) < unsigned(M) ? src[cc + 2] : 0.f;
+          v.w = unsigned(cc + 3) < unsigned(M) ? src[cc + 3] : 0.f;
+        }
+      }
+      float* dst = &box[j][pl][4 * q];
+      dst[0] = v.x;
+      dst[1] = v.y;
+      dst[2] = v.z;
+      dst[3] = v.w;
+    }
+    __syncthreads();
+    if (live) {
+      // box-local coordinates; fmax guards against a rounding-level dip below the box origin
+      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + hm - c0, 0.0);
+      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + hk - p0, 0.0);
+      const double fc0 = floor(fc), fp0 = floor(fp);
+      const float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
+      const int lc = int(fc0), lp = flat ? 0 : int(fp0);
+      // taps lie inside the staged box by construction (0 <= lc, lc+1 < BOXW; same for planes)
+      const float w00 = (1.0f - tz) * (1.0f - tx), w01 = (1.0f - tz) * tx;
+      const float w10 = tz * (1.0f - tx), w11 = tz * tx;
+      const int lp1 = flat ? lp : lp + 1;
+#pragma unroll
+      for (int j = 0; j < YB; ++j) {
+        const float* r0 = &box[j][lp][lc];
+        const float* r1 = &box[j][lp1][lc];
+        acc[j] += w00 * r0[0] + w01 * r0[1] + w10 * r1[0] + w11 * r1[1];
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int j = 0; j < YB; ++j) {
+    const int iy = y0 + j;
+    if (iy < N) {
+      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
+      *dst = accumulate ? *dst + acc[j] : acc[j];
+    }
+  }
+}
+
+// General view frames: full trilinear interpolation per voxel.  Each thread owns
+// voxel column (ix, iy) and ZB consecutive iz.
+template <int ZB>
+__global__ __launch_bounds__(256) void k_grid_gen(const float* __restrict__ stack,
+                                                  const ViewGeom* __restrict__ geom,
+                                                  float* __restrict__ vol, int N, int M, int K, int nb,
+                                                  int accumulate, int flat) {
+  const int ix = blockIdx.x * GT + (threadIdx.x % GT);
+  const int iy = blockIdx.y * GT + (threadIdx.x / GT);
+  const int z0 = blockIdx.z * ZB;
+  if (ix >= N || iy >= N) return;
+  const double c = 0.5 * (N - 1);
+  const double rx = ix - c, ry = iy - c;
+  const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
+  const size_t view_sz = size_t(M) * K * M;
+  float acc[ZB];
+#pragma unroll
+  for (int j = 0; j < ZB; ++j) acc[j] = 0.0f;
+  for (int n = 0; n < nb; ++n) {
+    const ViewGeom& g = geom[n];
+    const float* base = stack + size_t(n) * view_sz;
+    const double bc = g.u[0] * rx + g.u[1] * ry + hm;
+    const double br = g.v[0] * rx + g.v[1] * ry + hm;
+    const double bp = g.d[0] * rx + g.d[1] * ry + hk;
+#pragma unroll
+    for (int j = 0; j < ZB; ++j) {
+      const double rz = (z0 + j) - c;
+      const double fc = g.u[2] * rz + bc, fr = g.v[2] * rz + br, fp = g.d[2] * rz + bp;
+      const double fc0 = floor(fc), fr0 = floor(fr), fp0 = floor(fp);
+      const float tc = float(fc - fc0), tr = float(fr - fr0), tp = float(fp - fp0);
+      const int c0 = int(fc0), r0 = int(fr0), p0 = int(fp0);
+      const float wc0 = (unsigned(c0) < unsigned(M)) ? 1.0f - tc : 0.0f;
+      const float wc1 = (unsigned(c0 + 1) < unsigned(M)) ? tc : 0.0f;
+      const float wr0 = (unsigned(r0) < unsigned(M)) ? 1.0f - tr : 0.0f;
+      const float wr1 = (unsigned(r0 + 1) < unsigned(M)) ? tr : 0.0f;
+      const float wp0 = flat ? 1.0f : (unsigned(p0) < unsigned(K)) ? 1.0f - tp : 0.0f;
+      const float wp1 = flat ? 0.0f : (unsigned(p0 + 1) < unsigned(K)) ? tp : 0.0f;
+      const int c0c = min(max(c0, 0), M - 1), c1c = min(max(c0 + 1, 0), M - 1);
+      const int r0c = min(max(r0, 0), M - 1), r1c = min(max(r0 + 1, 0), M - 1);
+      const int p0c = min(max(p0, 0), K - 1), p1c = min(max(p0 + 1, 0), K - 1);
+      const float* a0 = base + (size_t(r0c) * K + p0c) * M;
+      const float* a1 = base + (size_t(r0c) * K + p1c) * M;
+      const float* b0 = base + (size_t(r1c) * K + p0c) * M;
+      const float* b1 = base + (size_t(r1c) * K + p1c) * M;
+      const float v0 = wc0 * a0[c0c] + wc1 * a0[c1c];
+      const float v1 = wc0 * a1[c0c] + wc1 * a1[c1c];
+      const float v2 = wc0 * b0[c0c] + wc1 * b0[c1c];
+      const float v3 = wc0 * b1[c0c] + wc1 * b1[c1c];
+      acc[j] += wr0 * (wp0 * v0 + wp1 * v1) + wr1 * (wp0 * v2 + wp1 * v3);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < ZB; ++j) {
+    const int iz = z0 + j;
+    if (iz < N) {
+      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
+      *dst = accumulate ? *dst + acc[j] : acc[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ plan tables (FP64)
+__device__ __forceinline__ double signed_q(int k, int M, double dx) {
+  const int ks = (k < (M + 1) / 2) ? k : k - M;  // fftfreq order
+  return double(ks) / (double(M) * dx);
+}
+
+__device__ __forceinline__ double2 filter_value(const FilterArgs& fa, const ViewGeom& g,
+                                                const double* wv, int ky, int kx, int n) {
+  const double qx = signed_q(kx, fa.M, fa.dx), qy = signed_q(ky, fa.M, fa.dx);
+  const double q2 = qx * qx + qy * qy;
+  double w;
+  if (fa.mode == 0) w = g.a * fabs(qx);
+  else if (fa.mode == 1) w = 2.0 * sqrt(q2) / double(fa.n_views);
+  else w = wv[(size_t(n) * fa.M + ky) * fa.M + kx];
+  const double omega = atan(fa.sigma);
+  const double cst = fa.lambda / (4.0 * M_PI * sqrt(1.0 + fa.sigma * fa.sigma));
+  const double chi = M_PI * fa.lambda * g.R * q2 - omega;
+  double sn, cs;
+  sincos(chi, &sn, &cs);
+  const double hre = sn / (sn * sn + fa.epsilon);
+  const double him = fa.ewald ? -cs / (cs * cs + fa.epsilon) : 0.0;
+  return make_double2(cst * w * hre, cst * w * him);
+}
+
+__global__ void k_filter_table(FilterArgs fa, const ViewGeom* __restrict__ geom,
+                               const double* __restrict__ wtab, float4* __restrict__ filt) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t per = size_t(fa.M) * fa.M;
+  if (i >= per * fa.n_views) return;
+  const int n = int(i / per);
+  const int ky = int((i % per) / fa.M), kx = int(i % fa.M);
+  const ViewGeom g = geom[n];
+  const double2 f = filter_value(fa, g, wtab, ky, kx, n);
+  const double2 fm = filter_value(fa, g, wtab, (fa.M - ky) % fa.M, (fa.M - kx) % fa.M, n);
+  // F_h = (F(k) + conj F(-k))/2, F_a = (F(k) - conj F(-k))/2
+  const double hr = 0.5 * (f.x + fm.x), hi = 0.5 * (f.y - fm.y);
+  const double ar = 0.5 * (f.x - fm.x), ai = 0.5 * (f.y + fm.y);
+  const double inv = 1.0 / (double(fa.M) * double(fa.M));
+  // G1 = (1+i) F_h / M^2,  G2 = -(1+i) F_a / M^2
+  float4 o;
+  o.x = float((hr - hi) * inv);
+  o.y = float((hr + hi) * inv);
+  o.z = float(-(ar - ai) * inv);
+  o.w = float(-(ar + ai) * inv);
+  filt[i] = o;
+}
+
+// Sampling matrix in 2^-32 fixed point (integer atomics: order independent).
+constexpr double kFix = 4294967296.0;
+
+__device__ __forceinline__ void sample_point(const FilterArgs& fa, const ViewGeom& g, int ky, int kx,
+                                             double* p) {
+  const double qx = signed_q(kx, fa.M, fa.dx), qy = signed_q(ky, fa.M, fa.dx);
+  const double qz = -double(fa.ewald) * fa.lambda * (qx * qx + qy * qy) * 0.5;
+  const double sc = double(fa.N) * fa.dx;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p[a] = (qx * g.u[a] + qy * g.v[a] + qz * g.d[a]) * sc;
+}
+
+__global__ void k_sampling_splat(FilterArgs fa, const ViewGeom* __restrict__ geom,
+                                 unsigned long long* __restrict__ smat) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t per = size_t(fa.M) * fa.M;
+  if (i >= per * fa.n_views) return;
+  const int n = int(i / per);
+  const int ky = int((i % per) / fa.M), kx = int(i % fa.M);
+  double p[3];
+  sample_point(fa, geom[n], ky, kx, p);
+  const int N = fa.N, lo = -(N / 2);
+  for (int sgn = 0; sgn < 2; ++sgn) {
+    double f[3];
+    int i0[3];
+    double t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      f[a] = (sgn ? -p[a] : p[a]) - lo;
+      const double fl = floor(f[a]);
+      i0[a] = int(fl);
+      t[a] = f[a] - fl;
+    }
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const int jx = i0[0] + cx, jy = i0[1] + cy, jz = i0[2] + cz;
+          if (unsigned(jx) >= unsigned(N) || unsigned(jy) >= unsigned(N) || unsigned(jz) >= unsigned(N))
+            continue;
+          const double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+          const unsigned long long fx = (unsigned long long)llrint(0.5 * w * kFix);
+          atomicAdd(&smat[(size_t(jz) * N + jy) * N + jx], fx);
+        }
+  }
+}
+
+__global__ void k_sampling_weights(FilterArgs fa, const ViewGeom* __restrict__ geom,
+                                   const unsigned long long* __restrict__ smat, double* __restrict__ wtab) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t per = size_t(fa.M) * fa.M;
+  if (i >= per * fa.n_views) return;
+  const int n = int(i / per);
+  const int ky = int((i % per) / fa.M), kx = int(i % fa.M);
+  double p[3];
+  sample_point(fa, geom[n], ky, kx, p);
+  const int N = fa.N, lo = -(N / 2), hi = (N + 1) / 2 - 1;
+  bool inside = true;
+  double t[3];
+  int i0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    inside = inside && (p[a] >= lo) && (p[a] <= hi);
+    const double f = p[a] - lo;
+    const double fl = floor(f);
+    i0[a] = int(fl);
+    t[a] = f - fl;
+  }
+  double shat = 0.0;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const int jx = i0[0] + cx, jy = i0[1] + cy, jz = i0[2] + cz;
+        if (unsigned(jx) >= unsigned(N) || unsigned(jy) >= unsigned(N) || unsigned(jz) >= unsigned(N))
+          continue;
+        const double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+        shat += w * (double(smat[(size_t(jz) * N + jy) * N + jx]) / kFix);
+      }
+  const double scale = double(fa.M) * fa.M / (double(N) * N * N * fa.dx);
+  wtab[i] = inside ? scale * shat / (shat * shat + fa.eps_sampling) : 0.0;
+}
+
+// ------------------------------------------------------------------ launchers
+template <int M>
+static hipError_t spectra_impl(const float* images, const float4* filt, const float2* tw, float4* q,
+                               int* status, double inv_iin, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_spectra<M>, dim3(nb), dim3(Shape<M>::T), 0, s, images, filt, tw, q, status,
+                     inv_iin);
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t planes_impl(const float4* q, const float2* prop, const float2* tw, float* stack, int K,
+                              int npairs, int nb, hipStream_t s) {
+  const int nb8 = (nb + 7) / 8;
+  hipLaunchKernelGGL(k_planes<M>, dim3(8 * npairs * nb8), dim3(Shape<M>::T), 0, s, q, prop, tw, stack,
+                     K, npairs, nb);
+  return hipGetLastError();
+}
+
+#define TOMO_DISPATCH_M(M_, CALL)                       \
+  switch (M_) {                                          \
+    case 16: return CALL(16);                            \
+    case 32: return CALL(32);                            \
+    case 48: return CALL(48);                            \
+    case 64: return CALL(64);                            \
+    case 80: return CALL(80);                            \
+    case 96: return CALL(96);                            \
+    case 128: return CALL(128);                          \
+    default: return hipErrorInvalidValue;                \
+  }
+
+hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
+                          float4* q, int* status, double inv_iin, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+#define CALL(MM) spectra_impl<MM>(images, filt, tw_fwd, q, status, inv_iin, nb, s)
+  TOMO_DISPATCH_M(M, CALL)
+#undef CALL
+}
+
+hipError_t launch_planes(int M, const float4* q, const float2* prop, const float2* tw_inv, float* stack,
+                         int K, int npairs, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+#define CALL(MM) planes_impl<MM>(q, prop, tw_inv, stack, K, npairs, nb, s)
+  TOMO_DISPATCH_M(M, CALL)
+#undef CALL
+}
+
+constexpr int kYB = 8;
+
+hipError_t launch_grid(bool axis_fast, const float* stack, const ViewGeom* geom, float* vol, int N, int M,
+                       int K, int nb, int accumulate, int flat, hipStream_t s) {
+  const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
+  if (axis_fast) {
+    // flat grid: (x, z) tiles x row blocks, row blocks padded to a multiple of 8 (one XCD each)
+    const int tiles = int(grid.x * grid.y);
+    const int yblocks8 = int((grid.z + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_grid_axis<kYB>, dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, stack, geom, vol,
+                       N, M, K, nb, accumulate, flat);
+  } else
+    hipLaunchKernelGGL(k_grid_gen<kYB>, grid, dim3(256), 0, s, stack, geom, vol, N, M, K, nb, accumulate,
+                       flat);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const double* wtab, float4* filt,
+                               hipStream_t s) {
+  const size_t total = size_t(fa.M) * fa.M * fa.n_views;
+  hipLaunchKernelGGL(k_filter_table, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, fa, geom, wtab,
+                     filt);
+  return hipGetLastError();
+}
+
+hipError_t launch_sampling(const FilterArgs& fa, const ViewGeom* geom, unsigned long long* smat,
+                           double* wtab, hipStream_t s) {
+  const size_t total = size_t(fa.M) * fa.M * fa.n_views;
+  const dim3 grid(unsigned((total + 255) / 256));
+  hipLaunchKernelGGL(k_sampling_splat, grid, dim3(256), 0, s, fa, geom, smat);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sampling_weights, grid, dim3(256), 0, s, fa, geom, smat, wtab);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectra_out(const float4* q, float2* out, int M, int nb, hipStream_t s) {
+  const size_t count = size_t(M) * M * nb;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spectra_out, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, q, out, count,
+                     float(double(M) * M));
+  return hipGetLastError();
+}
+
+}  // namespace tomo

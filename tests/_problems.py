@@ -1,0 +1,127 @@
+"""Seeded small problems shared by the GPU parity tests and smoke().
+
+Every problem is described once; the oracle and the HIP path receive the same
+float32 images (the oracle reads them as float64) and the same geometry.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from synth import forward, phantoms, scan
+
+
+@dataclass
+class Problem:
+    name: str
+    n_vox: int
+    n_pix: int
+    n_planes: int
+    voxel: float
+    wavelength: float
+    sigma: float
+    epsilon: float
+    ewald: int
+    weight_mode: str
+    dirs: np.ndarray
+    dist: np.ndarray
+    images: np.ndarray            # float32 [n, M, M]
+    vaxes: np.ndarray | None = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.dirs.shape[0]
+
+    def oracle_geometry(self):
+        import oracle
+        return oracle.Geometry(self.n_vox, self.n_pix, self.n_planes if self.ewald else 1, self.voxel,
+                               self.wavelength, self.sigma, self.epsilon, ewald=self.ewald,
+                               weight_mode=self.weight_mode)
+
+    def params(self, **kw):
+        from paper_2206_09151_amd import tomo
+        return tomo.Params(n_vox=self.n_vox, n_angles=self.n, voxel_size=self.voxel,
+                           wavelength=self.wavelength, sigma=self.sigma, epsilon=self.epsilon,
+                           n_pix=self.n_pix, n_planes=self.n_planes if self.ewald else 0, ewald=self.ewald,
+                           weight_mode=self.weight_mode, **kw)
+
+
+def _born(seed, n_vox, n_pix, dx, lam, dirs, dist, sigma, width=1.2, count=20):
+    ph = phantoms.draw_blobs(seed, n_vox, dx, 0.0, width * dx, 2e-5, sigma=sigma, count=count, support=0.4)
+    return forward.born_images(ph, dirs, n_pix, dx, lam, dist, sigma).astype(np.float32)
+
+
+def make(name: str) -> Problem:
+    dx = 1e-10
+    if name == "axis32":
+        n, N, M, K = 24, 32, 32, 32
+        dirs = scan.single_axis(n, 180.0)
+        dist = np.full(n, 50e-10)
+        lam, sig = 0.2e-10, 0.1
+        imgs = _born(11, N, M, dx, lam, dirs, dist, sig)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "ragged44":
+        n, N, M, K = 13, 44, 48, 44
+        dirs = scan.single_axis(n, 360.0, offset_deg=7.0)
+        dist = np.linspace(40e-10, 60e-10, n)
+        lam, sig = 0.1e-10, -0.2
+        imgs = _born(12, N, M, dx, lam, dirs, dist, sig)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "sphere45":
+        n, N, M, K = 11, 45, 48, 45
+        dirs = scan.uniform_sphere(13, n)
+        dist = np.full(n, 30e-10)
+        lam, sig = 0.1e-10, 0.0
+        imgs = _born(13, N, M, dx, lam, dirs, dist, sig)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+    if name == "pct64":
+        n, N, M = 30, 64, 64
+        dirs = scan.single_axis(n, 180.0)
+        dist = np.full(n, 0.1)
+        lam, sig, px = 1e-10, 0.01, 1e-6
+        ph = phantoms.draw_ellipsoids(14, 6, N, px, (1e-8, 5e-8), sig)
+        imgs = forward.project_fresnel_images(ph, dirs, M, px, lam, dist).astype(np.float32)
+        return Problem(name, N, M, 1, px, lam, sig, 1e-3, 0, "ramp_axis", dirs, dist, imgs)
+    if name == "sampling32":
+        n, N, M, K = 16, 32, 32, 32
+        dirs = scan.single_axis_jitter(15, n, 180.0, 5.0)
+        dist = np.full(n, 50e-10)
+        lam, sig = 0.1e-10, -0.1
+        imgs = _born(15, N, M, dx, lam, dirs, dist, sig)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "sampling", dirs, dist, imgs)
+    if name == "oddk16":
+        n, N, M, K = 5, 16, 16, 9
+        dirs = scan.single_axis(n, 180.0, offset_deg=3.0)
+        dist = np.full(n, 20e-10)
+        lam, sig = 0.3e-10, 0.2
+        imgs = _born(16, N, M, dx, lam, dirs, dist, sig, count=6)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "m80":
+        n, N, M, K = 4, 80, 80, 80
+        dirs = scan.single_axis(n, 180.0)
+        dist = np.full(n, 60e-10)
+        lam, sig = 0.05e-10, 0.0
+        imgs = _born(17, N, M, dx, lam, dirs, dist, sig, count=40)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "m96":
+        n, N, M, K = 3, 96, 96, 96
+        dirs = scan.single_axis(n, 180.0)
+        dist = np.full(n, 60e-10)
+        lam, sig = 0.05e-10, 0.0
+        imgs = _born(18, N, M, dx, lam, dirs, dist, sig, count=40)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "vaxes32":
+        n, N, M, K = 6, 32, 32, 32
+        dirs = scan.uniform_sphere(19, n)
+        rng = np.random.default_rng(1019)
+        vax = rng.standard_normal((n, 3))
+        dist = np.full(n, 40e-10)
+        lam, sig = 0.1e-10, 0.3
+        imgs = _born(19, N, M, dx, lam, dirs, dist, sig)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs, vaxes=vax)
+    raise KeyError(name)
+
+
+SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32"]
