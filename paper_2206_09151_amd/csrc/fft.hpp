@@ -190,6 +190,10 @@ struct Fft2Shape {
   static constexpr int SP = R2 * M + 2;       // exchange pitch per stage-1 output index s
   static constexpr int LDS_ELEMS = (M * TP > R1 * SP) ? M * TP : R1 * SP;
   static constexpr size_t LDS_BYTES = size_t(LDS_ELEMS) * sizeof(float2);
+  // component-split variant: each exchange moves the real parts, then the imaginary
+  // parts, through a float buffer of half the bytes
+  static constexpr int SPF = R2 * M + 4;      // float exchange pitch per s
+  static constexpr int LDS_SPLIT_FLOATS = (M * TP > R1 * SPF) ? M * TP : R1 * SPF;
   static_assert(R1 * R2 == M && R1 % R2 == 0, "M = R1*R2 with R2 | R1");
   static_assert(T <= 1024, "at most 1024 threads");
 };
@@ -263,6 +267,94 @@ __device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restric
       for (int k2 = 0; k2 < R2; ++k2) x[e * R2 + k2] = v[k2];
     }
   }
+}
+
+
+// Same transform, thread mapping and results as fft2_block, with every LDS exchange
+// done in two rounds -- real parts, then imaginary parts -- through a float buffer
+// of half the bytes (Shape::LDS_SPLIT_FLOATS), so two workgroups fit in one CU's
+// LDS and overlap each other's barriers.  No extra registers: a component is read
+// back into the slots its own values were written from.
+template <class S, bool INV>
+__device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __restrict__ lds,
+                                                 const float2* __restrict__ tw) {
+  constexpr int M = S::M, R1 = S::R1, R2 = S::R2, E = S::E, TP = S::TP, SPF = S::SPF;
+  const int t = threadIdx.x;
+  const int line = t % M;
+  int r_;
+  if constexpr (M % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / M);
+  else r_ = t / M;
+  const int r = r_;
+  const int sgc = t / M;
+
+  // ---- column pass, stage 1
+  Dft<R1, INV>::run(x);
+#pragma unroll
+  for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
+  // ---- exchange 1: x[s] of (line, r) -> thread (line, sgc) gets x[e*R2 + rr] = X1[s = sgc*E + e][rr]
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int s = 0; s < R1; ++s) lds[s * SPF + r * M + line] = comp ? x[s].y : x[s].x;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = sgc * E + e;
+#pragma unroll
+      for (int rr = 0; rr < R2; ++rr) {
+        const float v = lds[s * SPF + rr * M + line];
+        if (comp) x[e * R2 + rr].y = v;
+        else x[e * R2 + rr].x = v;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- column pass, stage 2 (radix R2 over rr), in place per e
+#pragma unroll
+  for (int e = 0; e < E; ++e) Dft<R2, INV>::run(&x[e * R2]);
+  // ---- transpose: (row Y = s + R1*k2, column line) -> thread (row line, r) gets columns r + R2*m
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = sgc * E + e;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) lds[(s + R1 * k2) * TP + line] = comp ? x[e * R2 + k2].y : x[e * R2 + k2].x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const float v = lds[line * TP + r + R2 * m];
+      if (comp) x[m].y = v;
+      else x[m].x = v;
+    }
+    __syncthreads();
+  }
+  // ---- row pass, stage 1
+  Dft<R1, INV>::run(x);
+#pragma unroll
+  for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
+  // ---- exchange 3: thread (sg = t % R2, y = t / R2) gets X1[s = sg*E + e][rr] of row y
+  const int sg = t % R2, yy = t / R2;
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int s = 0; s < R1; ++s) lds[s * SPF + r * M + line] = comp ? x[s].y : x[s].x;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int s = sg * E + e;
+#pragma unroll
+      for (int rr = 0; rr < R2; ++rr) {
+        const float v = lds[s * SPF + rr * M + yy];
+        if (comp) x[e * R2 + rr].y = v;
+        else x[e * R2 + rr].x = v;
+      }
+    }
+    if (comp == 0) __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) Dft<R2, INV>::run(&x[e * R2]);
 }
 
 }  // namespace tomo

@@ -104,6 +104,11 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
 // Workgroup -> (view, pair) mapping keeps all pairs of one view on one XCD
 // (workgroups are dealt to the 8 XCDs round robin), so the view's Q block is
 // fetched into one L2 only.
+// Exchanges through half-size LDS (two workgroups per CU) where the full block would
+// leave room for only one.
+template <int M>
+constexpr bool kSplit = (Shape<M>::LDS_BYTES > 80 * 1024);
+
 template <int M>
 __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict__ q,
                                                         const float2* __restrict__ prop,
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
                                                         float* __restrict__ stack, int K, int npairs,
                                                         int nb) {
   using S = Shape<M>;
-  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 lds[kSplit<M> ? (S::LDS_SPLIT_FLOATS + 1) / 2 : S::LDS_ELEMS];
   const int wg = blockIdx.x;
   const int xcd = wg & 7, k = wg >> 3;
   const int view = xcd + 8 * (k / npairs);
@@ -136,7 +141,8 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
     const float4 qq = qv[ky * M + line];
     x[m] = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
   }
-  fft2_block<S, true>(x, lds, tw_inv);
+  if constexpr (kSplit<M>) fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw_inv);
+  else fft2_block<S, true>(x, lds, tw_inv);
   const int sg = t % S::R2, y = t / S::R2;
   const int pa = p, pb = K - 1 - p;
   float* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
@@ -193,6 +199,9 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
                                                    const ViewGeom* __restrict__ geom,
                                                    float* __restrict__ vol, int N, int M, int K,
                                                    int nb, int accumulate, int flat) {
+  constexpr int Q4 = AX_BOXW / 4;                       // float4 per staged (row, plane)
+  constexpr int NE = YB * AX_BOXH * Q4;                 // float4 per staged view
+  constexpr int PER = (NE + 255) / 256;                 // float4 per thread
   __shared__ float box[YB][AX_BOXH][AX_BOXP];
   // Workgroups are dealt to the 8 XCDs round robin: give every tile of one voxel-row
   // block to the same XCD, so each detector row of the stacks is fetched into one L2.
@@ -212,47 +221,77 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
   const int rowoff = (M - N) / 2;
   const size_t plane_sz = size_t(K) * M;                // floats per detector row of the stack
   const bool vec4 = (M % 4) == 0;
+  const double ax = tx0 - c, bx = tx0 + GT - 1 - c, az = tz0 - c, bz = tz0 + GT - 1 - c;
+
+  // box origin of view n from the tile corners (uniform over the workgroup)
+  auto origin = [&](int n, int& c0, int& p0) {
+    const ViewGeom& g = geom[n];
+    const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
+    const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
+    c0 = int(floor(cmin)) & ~3;                         // 16-byte aligned column start
+    p0 = flat ? 0 : int(floor(pmin));
+  };
+  // this thread's share of view n's box, into registers (zero outside the stack)
+  auto fetch = [&](int n, int c0, int p0, float4 (&v)[PER]) {
+    const float* vbase = stack + size_t(n) * plane_sz * M;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int q = e % Q4, pl = (e / Q4) % AX_BOXH, j = e / (Q4 * AX_BOXH);
+      const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + 4 * q;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K)) {
+        const float* src = vbase + size_t(row) * plane_sz + size_t(pp) * M;
+        if (vec4 && cc >= 0 && cc + 3 < M) {
+          x = *reinterpret_cast<const float4*>(src + cc);
+        } else {
+          x.x = unsigned(cc) < unsigned(M) ? src[cc] : 0.f;
+          x.y = unsigned(cc + 1) < unsigned(M) ? src[cc + 1] : 0.f;
+          x.z = unsigned(cc + 2) < unsigned(M) ? src[cc + 2] : 0.f;
+          x.w = unsigned(cc + 3) < unsigned(M) ? src[cc + 3] : 0.f;
+        }
+      }
+      v[i] = x;
+    }
+  };
+  auto stage = [&](const float4 (&v)[PER]) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NE) {
+        const int q = e % Q4, pl = (e / Q4) % AX_BOXH, j = e / (Q4 * AX_BOXH);
+        float* dst = &box[j][pl][4 * q];
+        dst[0] = v[i].x;
+        dst[1] = v[i].y;
+        dst[2] = v[i].z;
+        dst[3] = v[i].w;
+      }
+    }
+  };
+
   float acc[YB];
 #pragma unroll
   for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
+  float4 buf[PER];
+  int c0 = 0, p0 = 0;
+  if (nb > 0) {
+    origin(0, c0, p0);
+    fetch(0, c0, p0, buf);
+  }
   for (int n = 0; n < nb; ++n) {
-    const ViewGeom& g = geom[n];
-    // box origin from the tile corners (uniform)
-    const double ax = tx0 - c, bx = tx0 + GT - 1 - c, az = tz0 - c, bz = tz0 + GT - 1 - c;
-    const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
-    const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
-    const int c0 = int(floor(cmin)) & ~3;               // 16-byte aligned column start
-    const int p0 = flat ? 0 : int(floor(pmin));
-    const float* vbase = stack + size_t(n) * plane_sz * M;
-    __syncthreads();                                    // previous view's reads are done
-    // stage [YB][BOXH][BOXW]: 7 float4 per (row, plane)
-    for (int e = threadIdx.x; e < YB * AX_BOXH * (AX_BOXW / 4); e += 256) {
-      const int q = e % (AX_BOXW / 4), pl = (e / (AX_BOXW / 4)) % AX_BOXH, j = e / ((AX_BOXW / 4) * AX_BOXH);
-      const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + 4 * q;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      const bool rok = (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K);
-      if (rok) {
-        const float* src = vbase + size_t(row) * plane_sz + size_t(pp) * M;
-        if (vec4 && cc >= 0 && cc + 3 < M) {
-          v = *reinterpret_cast<const float4*>(src + cc);
-        } else {
-          v.x = unsigned(cc) < unsigned(M) ? src[cc] : 0.f;
-          v.y = unsigned(cc + 1) < unsigned(M) ? src[cc + 1] : 0.f;
-          v.z = unsigned(cc + 2) < unsigned(M) ? src[cc + 2] : 0.f;
-          v.w = unsigned(cc + 3) < unsigned(M) ? src[cc + 3] : 0.f;
-        }
-      }
-      float* dst = &box[j][pl][4 * q];
-      dst[0] = v.x;
-      dst[1] = v.y;
-      dst[2] = v.z;
-      dst[3] = v.w;
-    }
+    __syncthreads();                                    // previous view's LDS reads are done
+    stage(buf);
     __syncthreads();
+    const int cc0 = c0, pp0 = p0;
+    if (n + 1 < nb) {                                   // next view's loads overlap this view's math
+      origin(n + 1, c0, p0);
+      fetch(n + 1, c0, p0, buf);
+    }
     if (live) {
+      const ViewGeom& g = geom[n];
       // box-local coordinates; fmax guards against a rounding-level dip below the box origin
-      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + hm - c0, 0.0);
-      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + hk - p0, 0.0);
+      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + hm - cc0, 0.0);
+      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + hk - pp0, 0.0);
       const double fc0 = floor(fc), fp0 = floor(fp);
       const float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
       const int lc = int(fc0), lp = flat ? 0 : int(fp0);
