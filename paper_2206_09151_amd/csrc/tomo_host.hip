@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tomo.h"
+#include "tomo.h"
 #include "tomo_internal.hpp"
 
 using tomo::ViewGeom;

@@ -261,10 +261,14 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
       if (e < NE) {
         const int q = e % Q4, pl = (e / Q4) % AX_BOXH, j = e / (Q4 * AX_BOXH);
         float* dst = &box[j][pl][4 * q];
-        dst[0] = v[i].x;
-        dst[1] = v[i].y;
-        dst[2] = v[i].z;
-        dst[3] = v[i].w;
+        if constexpr (AX_BOXP % 4 == 0) {
+          *reinterpret_cast<float4*>(dst) = v[i];
+        } else {
+          dst[0] = v[i].x;
+          dst[1] = v[i].y;
+          dst[2] = v[i].z;
+          dst[3] = v[i].w;
+        }
       }
     }
   };

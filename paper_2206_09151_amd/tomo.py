@@ -11,6 +11,10 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+# PyTorch is imported before the library is loaded so that libtomo.so binds to the HIP
+# runtime torch already loaded (same soname): one runtime owns the streams and the
+# device memory that are passed across the boundary.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtomo.so")
