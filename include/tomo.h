@@ -25,8 +25,8 @@
  *     within 1e-6 of +-y) unless vaxes gives it; u_n = v_n x d_n.
  *   - Depth planes z'_j = (j - (K-1)/2) * voxel_size, j = 0..K-1.  dist[n] = R_n
  *     is measured from the plane z' = 0 through the rotation centre.
- *   - Plane stack (tomo_backpropagate output / tomo_grid input): float32
- *     [nb][M][K][M], index [view][row][plane][col]; with ewald = 0, K = 1.
+ *   - Plane stack (tomo_backpropagate output / tomo_grid input): [nb][M][K][M] of the
+ *     plan's plane_dtype, index [view][row][plane][col]; with ewald = 0, K = 1.
  *   - Device pointers must be 256-byte aligned device allocations owned by the
  *     caller; they are never freed or retained by the library.
  *   - Streams are hipStream_t passed as void*; NULL means the null stream.
@@ -73,7 +73,12 @@ typedef enum {
  *                   reflection add half their weights; zero off the grid. */
 typedef enum { TOMO_RAMP_AXIS = 0, TOMO_RAMP_ISO = 1, TOMO_SAMPLING = 2 } tomo_weight_mode;
 
-/* Storage type of the plane stack.  Only TOMO_F32 is implemented. */
+/* Storage type of the plane stack.  Interpolation and accumulation are FP32 for all
+ * three.  TOMO_BF16 rounds each plane value to nearest even; TOMO_F16 first multiplies a
+ * view's planes by a power of two chosen from a bound on the view's plane values
+ * (2^14 / sum of spectral magnitudes, rounded to a power of two) so that they sit in
+ * the FP16 normal range; the plan keeps that per-view scale and tomo_grid divides it
+ * out, so FP16 stacks must be gridded by the plan that back-propagated them. */
 typedef enum { TOMO_F32 = 0, TOMO_BF16 = 1, TOMO_F16 = 2 } tomo_dtype;
 
 typedef struct {
@@ -89,7 +94,7 @@ typedef struct {
   double i_in;            /* flat-field intensity I_in (> 0; 0 -> 1) */
   int32_t ewald;          /* 1: eq. (11) with depth planes; 0: eq. (13), one plane */
   int32_t weight_mode;    /* tomo_weight_mode */
-  int32_t plane_dtype;    /* tomo_dtype; TOMO_F32 */
+  int32_t plane_dtype;    /* tomo_dtype of the plane stack */
   int32_t angle_batch;    /* views per internal batch of tomo_reconstruct; 0 -> automatic */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
                                  when plan tables + workspace would exceed it */
@@ -110,7 +115,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
 
 /* Back-propagate views [first, first+nb): contrast, 2D DFT, filter (eq. 11),
  * propagation to every depth plane (eq. 3), real part.  Writes the plane stacks
- * d_planes (device, float32 [nb][M][K][M], fully overwritten).
+ * d_planes (device, [nb][M][K][M] of plane_dtype, fully overwritten).
  * d_images: device float32 [nb][M][M], the images of those views.  Asynchronous:
  * an invalid image value raises TOMO_EDOMAIN at the next tomo_sync/tomo_reconstruct.
  * Uses the plan's spectrum slots of those views (calls on one plan are serial). */

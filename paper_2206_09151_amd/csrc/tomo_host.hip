@@ -27,7 +27,8 @@ struct tomo_plan_s {
   float2* d_tw_fwd = nullptr;   // [M]
   float2* d_tw_inv = nullptr;   // [M]
   float4* d_q = nullptr;        // [n][M][M]  filtered spectra of every view
-  float* d_stack = nullptr;     // [batch][M][K][M]
+  void* d_stack = nullptr;      // [batch][M][K][M] of the plane storage type
+  float* d_scale = nullptr;     // [n] FP16 plane scale per view (powers of two)
   int* d_status = nullptr;
   std::string err;
   // tracing: events around launches while timing is on
@@ -53,7 +54,9 @@ struct Resolved {
   size_t table_bytes, work_bytes;
 };
 
-size_t stack_view_bytes(int M, int K) { return size_t(M) * K * M * sizeof(float); }
+size_t dtype_bytes(int dtype) { return dtype == TOMO_F32 ? 4 : 2; }
+
+size_t stack_view_bytes(int M, int K, int dtype) { return size_t(M) * K * M * dtype_bytes(dtype); }
 
 // Resolve defaults and sizes; returns an error message or "" and fills r.
 std::string resolve(const tomo_params* p, Resolved* r) {
@@ -78,7 +81,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (r->K > 2 * r->N) return "n_planes must be <= 2 * n_vox";
   r->n = p->n_angles;
   r->npairs = (r->K + 1) / 2;
-  const size_t sv = stack_view_bytes(r->M, r->K);
+  const size_t sv = stack_view_bytes(r->M, r->K, p->plane_dtype);
   const size_t qv = size_t(r->M) * r->M * sizeof(float4);
   if (p->angle_batch > 0) {
     r->batch = std::min(p->angle_batch, r->n);
@@ -91,13 +94,12 @@ std::string resolve(const tomo_params* p, Resolved* r) {
     r->batch = std::min(b, r->n);
   }
   r->table_bytes = size_t(r->n) * sizeof(ViewGeom) + size_t(r->n) * qv + size_t(r->npairs) * r->M * 8 +
-                   2 * size_t(r->M) * 8 + 256;
+                   2 * size_t(r->M) * 8 + size_t(r->n) * 4 + 256;
   r->work_bytes = size_t(r->n) * qv + size_t(r->batch) * sv;
   return "";
 }
 
 std::string supported(const tomo_params* p, const Resolved& r) {
-  if (p->plane_dtype != TOMO_F32) return "only TOMO_F32 plane storage is implemented";
   if (!tomo::fft_supported(r.M)) {
     char b[160];
     std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128)", r.M);
@@ -205,6 +207,7 @@ void free_plan(tomo_plan_s* pl) {
   (void)hipFree(pl->d_tw_inv);
   (void)hipFree(pl->d_q);
   (void)hipFree(pl->d_stack);
+  (void)hipFree(pl->d_scale);
   (void)hipFree(pl->d_status);
 }
 
@@ -249,7 +252,7 @@ int32_t tomo_batch_capacity(tomo_plan_t plan) { return plan ? plan->batch : 0; }
 
 size_t tomo_stack_bytes(tomo_plan_t plan, int32_t nb) {
   if (!plan || nb < 0) return 0;
-  return size_t(nb) * stack_view_bytes(plan->M, plan->K);
+  return size_t(nb) * stack_view_bytes(plan->M, plan->K, plan->p.plane_dtype);
 }
 
 tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* vaxes, const double* dist,
@@ -344,7 +347,9 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       (e = dev_alloc(&pl->d_tw_fwd, size_t(r.M))) != hipSuccess ||
       (e = dev_alloc(&pl->d_tw_inv, size_t(r.M))) != hipSuccess ||
       (e = dev_alloc(&pl->d_q, mm * r.n)) != hipSuccess ||
-      (e = dev_alloc(&pl->d_stack, size_t(r.batch) * r.M * r.K * r.M)) != hipSuccess ||
+      (e = dev_alloc(reinterpret_cast<char**>(&pl->d_stack),
+                     size_t(r.batch) * stack_view_bytes(r.M, r.K, p->plane_dtype))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_scale, size_t(r.n))) != hipSuccess ||
       (e = dev_alloc(&pl->d_status, size_t(1))) != hipSuccess) {
     free_plan(pl);
     delete pl;
@@ -417,9 +422,10 @@ static tomo_status check_range(tomo_plan_t pl, int32_t first, int32_t nb) {
 // Spectra of views [first, first+nb) into the plan's per-view slots of d_q.
 static tomo_status run_spectra(tomo_plan_t pl, const float* d_images, int32_t first, int32_t nb, hipStream_t s) {
   const size_t mm = size_t(pl->M) * pl->M;
+  float* scale = pl->p.plane_dtype == TOMO_F16 ? pl->d_scale + first : nullptr;
   hipError_t e = timed(pl, 0, s, [&] {
     return tomo::launch_spectra(pl->M, d_images, pl->d_filt + size_t(first) * mm, pl->d_tw_fwd,
-                                pl->d_q + size_t(first) * mm, pl->d_status, 1.0 / pl->p.i_in, nb, s);
+                                pl->d_q + size_t(first) * mm, pl->d_status, 1.0 / pl->p.i_in, scale, nb, s);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "spectra kernel");
   return TOMO_OK;
@@ -437,8 +443,8 @@ tomo_status tomo_backpropagate(tomo_plan_t pl, const float* d_images, int32_t fi
   if ((st = run_spectra(pl, d_images, first, nb, s)) != TOMO_OK) return st;
   const size_t mm = size_t(pl->M) * pl->M;
   hipError_t e = timed(pl, 1, s, [&] {
-    return tomo::launch_planes(pl->M, pl->d_q + size_t(first) * mm, pl->d_prop, pl->d_tw_inv,
-                               static_cast<float*>(d_planes), pl->K, pl->npairs, nb, s);
+    return tomo::launch_planes(pl->M, pl->p.plane_dtype, pl->d_q + size_t(first) * mm, pl->d_prop, pl->d_tw_inv,
+                               d_planes, pl->K, pl->npairs, nb, pl->d_scale + first, s);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
   return TOMO_OK;
@@ -454,8 +460,8 @@ tomo_status tomo_grid(tomo_plan_t pl, const void* d_planes, int32_t first, int32
     return fail(pl, TOMO_EINVAL, "view range [first, first+nb) outside [0, n_angles)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = timed(pl, 2, s, [&] {
-    return tomo::launch_grid(pl->axis_fast, static_cast<const float*>(d_planes), pl->d_geom + first, d_volume,
-                             pl->N, pl->M, pl->K, nb, 1, pl->p.ewald ? 0 : 1, s);
+    return tomo::launch_grid(pl->axis_fast, pl->p.plane_dtype, d_planes, pl->d_geom + first, pl->d_scale + first,
+                             d_volume, pl->N, pl->M, pl->K, nb, 1, pl->p.ewald ? 0 : 1, s);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
   return TOMO_OK;
@@ -491,13 +497,14 @@ tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_vol
   for (int first = 0; first < pl->n; first += pl->batch) {
     const int nb = std::min(pl->batch, pl->n - first);
     hipError_t e = timed(pl, 1, s, [&] {
-      return tomo::launch_planes(pl->M, pl->d_q + size_t(first) * mm, pl->d_prop, pl->d_tw_inv, pl->d_stack,
-                                 pl->K, pl->npairs, nb, s);
+      return tomo::launch_planes(pl->M, pl->p.plane_dtype, pl->d_q + size_t(first) * mm, pl->d_prop,
+                                 pl->d_tw_inv, pl->d_stack, pl->K, pl->npairs, nb, pl->d_scale + first, s);
     });
     if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
     e = timed(pl, 2, s, [&] {
-      return tomo::launch_grid(pl->axis_fast, pl->d_stack, pl->d_geom + first, d_volume, pl->N, pl->M, pl->K,
-                               nb, first > 0 ? 1 : 0, pl->p.ewald ? 0 : 1, s);
+      return tomo::launch_grid(pl->axis_fast, pl->p.plane_dtype, pl->d_stack, pl->d_geom + first,
+                               pl->d_scale + first, d_volume, pl->N, pl->M, pl->K, nb, first > 0 ? 1 : 0,
+                               pl->p.ewald ? 0 : 1, s);
     });
     if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
   }

@@ -25,15 +25,17 @@ bool fft_supported(int M);
 int fft_threads(int M);
 
 // g = ln(I/I_in) -> 2D DFT -> (G1 G, G2 G) for nb views.  filt, q: [nb][M][M] float4.
+// scale (FP16 planes only, else NULL): per-view power-of-two plane scale, [nb].
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
-                          float4* q, int* status, double inv_iin, int nb, hipStream_t s);
-// Plane pairs (p, K-1-p), p < npairs, of nb views -> stack [nb][M][K][M].
-hipError_t launch_planes(int M, const float4* q, const float2* prop, const float2* tw_inv,
-                         float* stack, int K, int npairs, int nb, hipStream_t s);
+                          float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s);
+// Plane pairs (p, K-1-p), p < npairs, of nb views -> stack [nb][M][K][M] of dtype
+// (0 FP32, 1 BF16, 2 FP16 scaled by scale[view]).
+hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, const float2* tw_inv,
+                         void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s);
 // Trilinear gather of nb stacks into V[N][N][N] (accumulate: V += ..., else V = ...).
 // flat: one plane without depth axis (no Ewald curvature): bilinear in the detector plane.
-hipError_t launch_grid(bool axis_fast, const float* stack, const ViewGeom* geom, float* vol, int N,
-                       int M, int K, int nb, int accumulate, int flat, hipStream_t s);
+hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
+                       float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s);
 // Plan-time tables.
 hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const double* wtab,
                                float4* filt, hipStream_t s);

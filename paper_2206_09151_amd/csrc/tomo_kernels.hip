@@ -15,6 +15,8 @@
 //               (text after eq. 11), summed over the batch's views in ascending
 //               order in registers, then one read-modify-write of V (no atomics).
 //   k_filter_table, k_sampling_*: plan-time tables in FP64, stored FP32.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -61,9 +63,10 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
                                                          const float4* __restrict__ filt,
                                                          const float2* __restrict__ tw_fwd,
                                                          float4* __restrict__ q, int* __restrict__ status,
-                                                         double inv_iin) {
+                                                         double inv_iin, float* __restrict__ scale) {
   using S = Shape<M>;
   __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float red[S::T / 64];
   const int t = threadIdx.x;
   const int view = blockIdx.x;
   const int line = t % M, r = t / M;
@@ -83,6 +86,7 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
   fft2_block<S, false>(x, lds, tw_fwd);
   const int sg = t % S::R2, ky = t / S::R2;
   const size_t row = (size_t(view) * M + ky) * M;
+  float l1 = 0.0f;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) {
 #pragma unroll
@@ -96,6 +100,21 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
       o.z = f.z * gg.x - f.w * gg.y;
       o.w = f.z * gg.y + f.w * gg.x;
       q[row + kx] = o;
+      l1 += fabsf(o.x) + fabsf(o.y) + fabsf(o.z) + fabsf(o.w);
+    }
+  }
+  if (scale) {
+    // FP16 plane storage: every plane value of this view is bounded by
+    // sum_k |cos Q1 + sin Q2| <= sum_k (|Q1| + |Q2|) <= l1; scale by the power of two that
+    // puts this bound at 2^14 (exact scaling, values stay below the FP16 maximum).
+    // Fixed-order reduction: wave sums, then the wave partials in order.
+    for (int off = 32; off > 0; off >>= 1) l1 += __shfl_xor(l1, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = l1;
+    __syncthreads();
+    if (t == 0) {
+      float tot = 0.0f;
+      for (int w = 0; w < S::T / 64; ++w) tot += red[w];
+      scale[view] = tot > 0.0f ? exp2f(14.0f - ceilf(log2f(tot))) : 1.0f;
     }
   }
 }
@@ -109,12 +128,31 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
 template <int M>
 constexpr bool kSplit = (Shape<M>::LDS_BYTES > 80 * 1024);
 
-template <int M>
+// Plane storage types: FP32, BF16 (round to nearest even), FP16 (per-view power-of-two scale).
+template <class T>
+__device__ __forceinline__ T to_store(float v);
+template <>
+__device__ __forceinline__ float to_store<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ __hip_bfloat16 to_store<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+template <>
+__device__ __forceinline__ __half to_store<__half>(float v) { return __float2half_rn(v); }
+
+template <class T>
+__device__ __forceinline__ float from_store(T v);
+template <>
+__device__ __forceinline__ float from_store<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float from_store<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
+template <>
+__device__ __forceinline__ float from_store<__half>(__half v) { return __half2float(v); }
+
+template <int M, class OutT>
 __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict__ q,
                                                         const float2* __restrict__ prop,
                                                         const float2* __restrict__ tw_inv,
-                                                        float* __restrict__ stack, int K, int npairs,
-                                                        int nb) {
+                                                        OutT* __restrict__ stack, int K, int npairs,
+                                                        int nb, const float* __restrict__ scale) {
   using S = Shape<M>;
   __shared__ float2 lds[kSplit<M> ? (S::LDS_SPLIT_FLOATS + 1) / 2 : S::LDS_ELEMS];
   const int wg = blockIdx.x;
@@ -145,14 +183,15 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
   else fft2_block<S, true>(x, lds, tw_inv);
   const int sg = t % S::R2, y = t / S::R2;
   const int pa = p, pb = K - 1 - p;
-  float* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
-  float* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
+  const float sc = scale ? scale[view] : 1.0f;
+  OutT* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
+  OutT* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
 #pragma unroll
   for (int k2 = 0; k2 < S::R2; ++k2) {
 #pragma unroll
     for (int e = 0; e < S::E; ++e) {
       const int xc = sg * S::E + e + S::R1 * k2;
-      rowa[xc] = x[e * S::R2 + k2].x;
+      rowa[xc] = to_store<OutT>(x[e * S::R2 + k2].x * sc);
     }
   }
   if (pb != pa) {
@@ -161,7 +200,7 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
 #pragma unroll
       for (int e = 0; e < S::E; ++e) {
         const int xc = sg * S::E + e + S::R1 * k2;
-        rowb[xc] = x[e * S::R2 + k2].y;
+        rowb[xc] = to_store<OutT>(x[e * S::R2 + k2].y * sc);
       }
     }
   }
@@ -186,23 +225,58 @@ constexpr int GT = 16;  // voxel tile edge (x) x (z or y) per 256-thread workgro
 // (plane, col), shared by the YB voxel rows of a thread.
 //
 // Per view, the workgroup's 16 x 16 (x, z) tile maps into a rotated square of the
-// (plane, col) grid.  Its bounding box (at most 24 x 24 for a 16 x 16 tile; the
-// column start is rounded down to a multiple of 4 for 16-byte loads) is staged into
-// LDS for the YB rows with coalesced vector loads, zero outside the stack, so the
-// bilinear taps are plain LDS reads with no bounds masks.
+// (plane, col) grid.  Its bounding box (at most 24 planes x 24 columns for a 16 x 16
+// tile; the column start is rounded down to a 16-byte boundary) is staged into LDS as
+// FP32 for the YB rows with 16-byte loads, zero outside the stack, so the bilinear taps
+// are plain LDS reads with no bounds masks.  The next view's box is loaded into
+// registers while the current view is interpolated.
+template <class InT>
+struct AxisBox;
+template <>
+struct AxisBox<float> {   // 4 values per 16-byte chunk
+  static constexpr int VEC = 4, BOXW = 28, BOXP = 28;
+};
+template <>
+struct AxisBox<__hip_bfloat16> {   // 8 values per chunk
+  static constexpr int VEC = 8, BOXW = 32, BOXP = 36;
+};
+template <>
+struct AxisBox<__half> {
+  static constexpr int VEC = 8, BOXW = 32, BOXP = 36;
+};
 constexpr int AX_BOXH = 24;     // planes staged per row
-constexpr int AX_BOXW = 28;     // columns staged per row (24 + alignment slack), 7 float4
-constexpr int AX_BOXP = 29;     // LDS pitch (odd: spreads the rows over the banks)
 
-template <int YB>
-__global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ stack,
+union Chunk16 {
+  uint4 u;
+  float f[4];
+  unsigned short h[8];
+};
+
+template <class InT>
+__device__ __forceinline__ float chunk_value(const Chunk16& c, int k);
+template <>
+__device__ __forceinline__ float chunk_value<float>(const Chunk16& c, int k) { return c.f[k]; }
+template <>
+__device__ __forceinline__ float chunk_value<__hip_bfloat16>(const Chunk16& c, int k) {
+  return __uint_as_float(unsigned(c.h[k]) << 16);
+}
+template <>
+__device__ __forceinline__ float chunk_value<__half>(const Chunk16& c, int k) {
+  return __half2float(__ushort_as_half(c.h[k]));
+}
+
+template <int YB, class InT>
+__global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack,
                                                    const ViewGeom* __restrict__ geom,
+                                                   const float* __restrict__ scale,
                                                    float* __restrict__ vol, int N, int M, int K,
                                                    int nb, int accumulate, int flat) {
-  constexpr int Q4 = AX_BOXW / 4;                       // float4 per staged (row, plane)
-  constexpr int NE = YB * AX_BOXH * Q4;                 // float4 per staged view
-  constexpr int PER = (NE + 255) / 256;                 // float4 per thread
-  __shared__ float box[YB][AX_BOXH][AX_BOXP];
+  using B = AxisBox<InT>;
+  constexpr int VEC = B::VEC, BOXW = B::BOXW, BOXP = B::BOXP;
+  constexpr int QN = BOXW / VEC;                        // chunks per staged (row, plane)
+  constexpr int NE = YB * AX_BOXH * QN;                 // chunks per staged view
+  constexpr int PER = (NE + 255) / 256;                 // chunks per thread
+  __shared__ float box[YB][AX_BOXH][BOXP];
   // Workgroups are dealt to the 8 XCDs round robin: give every tile of one voxel-row
   // block to the same XCD, so each detector row of the stacks is fetched into one L2.
   const int ntx = (N + GT - 1) / GT;
@@ -219,8 +293,8 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
   const double rx = ix - c, rz = iz - c;
   const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
   const int rowoff = (M - N) / 2;
-  const size_t plane_sz = size_t(K) * M;                // floats per detector row of the stack
-  const bool vec4 = (M % 4) == 0;
+  const size_t plane_sz = size_t(K) * M;                // values per detector row of the stack
+  const bool vec = (M % VEC) == 0;
   const double ax = tx0 - c, bx = tx0 + GT - 1 - c, az = tz0 - c, bz = tz0 + GT - 1 - c;
 
   // box origin of view n from the tile corners (uniform over the workgroup)
@@ -228,47 +302,58 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
     const ViewGeom& g = geom[n];
     const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
     const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
-    c0 = int(floor(cmin)) & ~3;                         // 16-byte aligned column start
+    c0 = int(floor(cmin)) & ~(VEC - 1);                 // 16-byte aligned column start
     p0 = flat ? 0 : int(floor(pmin));
   };
-  // this thread's share of view n's box, into registers (zero outside the stack)
-  auto fetch = [&](int n, int c0, int p0, float4 (&v)[PER]) {
-    const float* vbase = stack + size_t(n) * plane_sz * M;
+  // this thread's share of view n's box, into registers.  Every load reads a clamped,
+  // in-bounds address (no divergent zero-initialisation, so the loads stay in flight);
+  // slots outside the stack are marked in `valid` and zeroed when staged.
+  auto fetch = [&](int n, int c0, int p0, uint4 (&v)[PER], unsigned& valid) {
+    const InT* vbase = stack + size_t(n) * plane_sz * M;
+    valid = 0u;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 256 * i;
-      const int q = e % Q4, pl = (e / Q4) % AX_BOXH, j = e / (Q4 * AX_BOXH);
-      const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + 4 * q;
-      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K)) {
-        const float* src = vbase + size_t(row) * plane_sz + size_t(pp) * M;
-        if (vec4 && cc >= 0 && cc + 3 < M) {
-          x = *reinterpret_cast<const float4*>(src + cc);
-        } else {
-          x.x = unsigned(cc) < unsigned(M) ? src[cc] : 0.f;
-          x.y = unsigned(cc + 1) < unsigned(M) ? src[cc + 1] : 0.f;
-          x.z = unsigned(cc + 2) < unsigned(M) ? src[cc + 2] : 0.f;
-          x.w = unsigned(cc + 3) < unsigned(M) ? src[cc + 3] : 0.f;
+      const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
+      const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + VEC * q;
+      const bool ok = e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) &&
+                      cc >= 0 && cc < M;
+      valid |= ok ? (1u << i) : 0u;
+      const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
+      const InT* src = vbase + (size_t(rowc) * K + ppc) * M;
+      if (vec) {
+        // M and cc are multiples of VEC: a chunk lies wholly inside or wholly outside the row
+        const int ccc = min(max(cc, 0), M - VEC);
+        v[i] = *reinterpret_cast<const uint4*>(src + ccc);
+      } else {
+        Chunk16 x;
+#pragma unroll
+        for (int kk = 0; kk < VEC; ++kk) {
+          const int ce = min(max(cc + kk, 0), M - 1);
+          const float fv = from_store<InT>(src[ce]);
+          const bool ek = unsigned(cc + kk) < unsigned(M);
+          if constexpr (VEC == 4) x.f[kk] = ek ? fv : 0.0f;
+          else x.h[kk] = ek ? reinterpret_cast<const unsigned short*>(src)[ce] : (unsigned short)0;
         }
+        v[i] = x.u;
+        if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K))
+          valid |= (1u << i);                            // partial chunks carry their own zeros
       }
-      v[i] = x;
     }
   };
-  auto stage = [&](const float4 (&v)[PER]) {
+  auto stage = [&](const uint4 (&v)[PER], unsigned valid) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 256 * i;
       if (e < NE) {
-        const int q = e % Q4, pl = (e / Q4) % AX_BOXH, j = e / (Q4 * AX_BOXH);
-        float* dst = &box[j][pl][4 * q];
-        if constexpr (AX_BOXP % 4 == 0) {
-          *reinterpret_cast<float4*>(dst) = v[i];
-        } else {
-          dst[0] = v[i].x;
-          dst[1] = v[i].y;
-          dst[2] = v[i].z;
-          dst[3] = v[i].w;
-        }
+        const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
+        Chunk16 x;
+        x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
+        float* dst = &box[j][pl][VEC * q];
+#pragma unroll
+        for (int h = 0; h < VEC; h += 4)
+          *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
+                                                            chunk_value<InT>(x, h + 2), chunk_value<InT>(x, h + 3));
       }
     }
   };
@@ -276,23 +361,25 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
   float acc[YB];
 #pragma unroll
   for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
-  float4 buf[PER];
+  uint4 buf[PER];
+  unsigned valid = 0u;
   int c0 = 0, p0 = 0;
   if (nb > 0) {
     origin(0, c0, p0);
-    fetch(0, c0, p0, buf);
+    fetch(0, c0, p0, buf, valid);
   }
   for (int n = 0; n < nb; ++n) {
     __syncthreads();                                    // previous view's LDS reads are done
-    stage(buf);
+    stage(buf, valid);
     __syncthreads();
     const int cc0 = c0, pp0 = p0;
     if (n + 1 < nb) {                                   // next view's loads overlap this view's math
       origin(n + 1, c0, p0);
-      fetch(n + 1, c0, p0, buf);
+      fetch(n + 1, c0, p0, buf, valid);
     }
     if (live) {
       const ViewGeom& g = geom[n];
+      const float inv = scale ? 1.0f / scale[n] : 1.0f;  // exact: the scale is a power of two
       // box-local coordinates; fmax guards against a rounding-level dip below the box origin
       const double fc = fmax(g.u[0] * rx + g.u[2] * rz + hm - cc0, 0.0);
       const double fp = fmax(g.d[0] * rx + g.d[2] * rz + hk - pp0, 0.0);
@@ -300,8 +387,8 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
       const float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
       const int lc = int(fc0), lp = flat ? 0 : int(fp0);
       // taps lie inside the staged box by construction (0 <= lc, lc+1 < BOXW; same for planes)
-      const float w00 = (1.0f - tz) * (1.0f - tx), w01 = (1.0f - tz) * tx;
-      const float w10 = tz * (1.0f - tx), w11 = tz * tx;
+      const float w00 = (1.0f - tz) * (1.0f - tx) * inv, w01 = (1.0f - tz) * tx * inv;
+      const float w10 = tz * (1.0f - tx) * inv, w11 = tz * tx * inv;
       const int lp1 = flat ? lp : lp + 1;
 #pragma unroll
       for (int j = 0; j < YB; ++j) {
@@ -324,9 +411,10 @@ __global__ __launch_bounds__(256) void k_grid_axis(const float* __restrict__ sta
 
 // General view frames: full trilinear interpolation per voxel.  Each thread owns
 // voxel column (ix, iy) and ZB consecutive iz.
-template <int ZB>
-__global__ __launch_bounds__(256) void k_grid_gen(const float* __restrict__ stack,
+template <int ZB, class InT>
+__global__ __launch_bounds__(256) void k_grid_gen(const InT* __restrict__ stack,
                                                   const ViewGeom* __restrict__ geom,
+                                                  const float* __restrict__ scale,
                                                   float* __restrict__ vol, int N, int M, int K, int nb,
                                                   int accumulate, int flat) {
   const int ix = blockIdx.x * GT + (threadIdx.x % GT);
@@ -342,7 +430,8 @@ __global__ __launch_bounds__(256) void k_grid_gen(const float* __restrict__ stac
   for (int j = 0; j < ZB; ++j) acc[j] = 0.0f;
   for (int n = 0; n < nb; ++n) {
     const ViewGeom& g = geom[n];
-    const float* base = stack + size_t(n) * view_sz;
+    const InT* base = stack + size_t(n) * view_sz;
+    const float inv = scale ? 1.0f / scale[n] : 1.0f;   // exact: the scale is a power of two
     const double bc = g.u[0] * rx + g.u[1] * ry + hm;
     const double br = g.v[0] * rx + g.v[1] * ry + hm;
     const double bp = g.d[0] * rx + g.d[1] * ry + hk;
@@ -362,15 +451,15 @@ __global__ __launch_bounds__(256) void k_grid_gen(const float* __restrict__ stac
       const int c0c = min(max(c0, 0), M - 1), c1c = min(max(c0 + 1, 0), M - 1);
       const int r0c = min(max(r0, 0), M - 1), r1c = min(max(r0 + 1, 0), M - 1);
       const int p0c = min(max(p0, 0), K - 1), p1c = min(max(p0 + 1, 0), K - 1);
-      const float* a0 = base + (size_t(r0c) * K + p0c) * M;
-      const float* a1 = base + (size_t(r0c) * K + p1c) * M;
-      const float* b0 = base + (size_t(r1c) * K + p0c) * M;
-      const float* b1 = base + (size_t(r1c) * K + p1c) * M;
-      const float v0 = wc0 * a0[c0c] + wc1 * a0[c1c];
-      const float v1 = wc0 * a1[c0c] + wc1 * a1[c1c];
-      const float v2 = wc0 * b0[c0c] + wc1 * b0[c1c];
-      const float v3 = wc0 * b1[c0c] + wc1 * b1[c1c];
-      acc[j] += wr0 * (wp0 * v0 + wp1 * v1) + wr1 * (wp0 * v2 + wp1 * v3);
+      const InT* a0 = base + (size_t(r0c) * K + p0c) * M;
+      const InT* a1 = base + (size_t(r0c) * K + p1c) * M;
+      const InT* b0 = base + (size_t(r1c) * K + p0c) * M;
+      const InT* b1 = base + (size_t(r1c) * K + p1c) * M;
+      const float v0 = wc0 * from_store<InT>(a0[c0c]) + wc1 * from_store<InT>(a0[c1c]);
+      const float v1 = wc0 * from_store<InT>(a1[c0c]) + wc1 * from_store<InT>(a1[c1c]);
+      const float v2 = wc0 * from_store<InT>(b0[c0c]) + wc1 * from_store<InT>(b0[c1c]);
+      const float v3 = wc0 * from_store<InT>(b1[c0c]) + wc1 * from_store<InT>(b1[c1c]);
+      acc[j] += inv * (wr0 * (wp0 * v0 + wp1 * v1) + wr1 * (wp0 * v2 + wp1 * v3));
     }
   }
 #pragma unroll
@@ -514,19 +603,30 @@ __global__ void k_sampling_weights(FilterArgs fa, const ViewGeom* __restrict__ g
 // ------------------------------------------------------------------ launchers
 template <int M>
 static hipError_t spectra_impl(const float* images, const float4* filt, const float2* tw, float4* q,
-                               int* status, double inv_iin, int nb, hipStream_t s) {
+                               int* status, double inv_iin, float* scale, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_spectra<M>, dim3(nb), dim3(Shape<M>::T), 0, s, images, filt, tw, q, status,
-                     inv_iin);
+                     inv_iin, scale);
+  return hipGetLastError();
+}
+
+template <int M, class OutT>
+static hipError_t planes_impl(const float4* q, const float2* prop, const float2* tw, void* stack, int K,
+                              int npairs, int nb, const float* scale, hipStream_t s) {
+  const int nb8 = (nb + 7) / 8;
+  hipLaunchKernelGGL((k_planes<M, OutT>), dim3(8 * npairs * nb8), dim3(Shape<M>::T), 0, s, q, prop, tw,
+                     static_cast<OutT*>(stack), K, npairs, nb, scale);
   return hipGetLastError();
 }
 
 template <int M>
-static hipError_t planes_impl(const float4* q, const float2* prop, const float2* tw, float* stack, int K,
-                              int npairs, int nb, hipStream_t s) {
-  const int nb8 = (nb + 7) / 8;
-  hipLaunchKernelGGL(k_planes<M>, dim3(8 * npairs * nb8), dim3(Shape<M>::T), 0, s, q, prop, tw, stack,
-                     K, npairs, nb);
-  return hipGetLastError();
+static hipError_t planes_dtype(int dtype, const float4* q, const float2* prop, const float2* tw, void* stack,
+                               int K, int npairs, int nb, const float* scale, hipStream_t s) {
+  switch (dtype) {
+    case 0: return planes_impl<M, float>(q, prop, tw, stack, K, npairs, nb, nullptr, s);
+    case 1: return planes_impl<M, __hip_bfloat16>(q, prop, tw, stack, K, npairs, nb, nullptr, s);
+    case 2: return planes_impl<M, __half>(q, prop, tw, stack, K, npairs, nb, scale, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 #define TOMO_DISPATCH_M(M_, CALL)                       \
@@ -542,36 +642,50 @@ static hipError_t planes_impl(const float4* q, const float2* prop, const float2*
   }
 
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
-                          float4* q, int* status, double inv_iin, int nb, hipStream_t s) {
+                          float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-#define CALL(MM) spectra_impl<MM>(images, filt, tw_fwd, q, status, inv_iin, nb, s)
+#define CALL(MM) spectra_impl<MM>(images, filt, tw_fwd, q, status, inv_iin, scale, nb, s)
   TOMO_DISPATCH_M(M, CALL)
 #undef CALL
 }
 
-hipError_t launch_planes(int M, const float4* q, const float2* prop, const float2* tw_inv, float* stack,
-                         int K, int npairs, int nb, hipStream_t s) {
+hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, const float2* tw_inv,
+                         void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-#define CALL(MM) planes_impl<MM>(q, prop, tw_inv, stack, K, npairs, nb, s)
+#define CALL(MM) planes_dtype<MM>(dtype, q, prop, tw_inv, stack, K, npairs, nb, scale, s)
   TOMO_DISPATCH_M(M, CALL)
 #undef CALL
 }
 
 constexpr int kYB = 8;
 
-hipError_t launch_grid(bool axis_fast, const float* stack, const ViewGeom* geom, float* vol, int N, int M,
-                       int K, int nb, int accumulate, int flat, hipStream_t s) {
+template <class InT>
+static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* geom, const float* scale,
+                            float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
+  const InT* st = static_cast<const InT*>(stack);
   if (axis_fast) {
     // flat grid: (x, z) tiles x row blocks, row blocks padded to a multiple of 8 (one XCD each)
     const int tiles = int(grid.x * grid.y);
     const int yblocks8 = int((grid.z + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_grid_axis<kYB>, dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, stack, geom, vol,
-                       N, M, K, nb, accumulate, flat);
-  } else
-    hipLaunchKernelGGL(k_grid_gen<kYB>, grid, dim3(256), 0, s, stack, geom, vol, N, M, K, nb, accumulate,
-                       flat);
+    hipLaunchKernelGGL((k_grid_axis<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
+                       scale, vol, N, M, K, nb, accumulate, flat);
+  } else {
+    hipLaunchKernelGGL((k_grid_gen<kYB, InT>), grid, dim3(256), 0, s, st, geom, scale, vol, N, M, K, nb,
+                       accumulate, flat);
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
+                       float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
+  switch (dtype) {
+    case 0: return grid_impl<float>(axis_fast, stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+    case 1:
+      return grid_impl<__hip_bfloat16>(axis_fast, stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+    case 2: return grid_impl<__half>(axis_fast, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const double* wtab, float4* filt,

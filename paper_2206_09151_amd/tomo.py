@@ -172,6 +172,11 @@ class Plan:
     def stack_shape(self, nb: int) -> tuple:
         return (nb, self.M, self.K, self.M)
 
+    @property
+    def stack_dtype(self):
+        """torch dtype of the plane stack (plane_dtype)."""
+        return {F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[self.params.plane_dtype]
+
     # ---------------------------------------------------------------- entry points
     def backpropagate(self, images, first: int, nb: int, planes, stream=None):
         self._check(_LIB.tomo_backpropagate(self._h, _dptr(images), first, nb, _dptr(planes),

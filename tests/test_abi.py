@@ -88,11 +88,17 @@ def test_plan_rejects_ramp_axis_off_axis_direction():
     assert st == tomo.EINVAL and "y axis" in err
 
 
-def test_plan_unsupported_sizes_and_dtypes():
+def test_plan_unsupported_sizes_and_bad_dtype():
     st, err = _plan_status(_params(n_pix=100))
     assert st == tomo.EUNSUPPORTED and "n_pix" in err
-    st, err = _plan_status(_params(plane_dtype=tomo.BF16))
-    assert st == tomo.EUNSUPPORTED
+    st, err = _plan_status(_params(plane_dtype=7))
+    assert st == tomo.EINVAL and "plane_dtype" in err
+
+
+def test_workspace_halves_with_16bit_planes():
+    p32 = tomo.workspace_bytes(_params(angle_batch=4))
+    p16 = tomo.workspace_bytes(_params(angle_batch=4, plane_dtype=tomo.BF16))
+    assert p32 - p16 == 4 * 32 * 32 * 32 * 2
 
 
 def test_plan_workspace_limit_gives_enomem():

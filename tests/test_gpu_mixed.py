@@ -1,0 +1,63 @@
+"""Mixed-precision plane storage (BF16, FP16 with a per-view power-of-two scale):
+interpolation and accumulation stay FP32; the error against the FP64 oracle is
+reported and bounded.
+
+Bound: each stored plane value carries a relative rounding error <= u (BF16
+u = 2^-9, FP16 u = 2^-11).  The gridded volume is a signed sum of such values,
+so its relative error is u times a cancellation factor (the ratio of the sum of
+|terms| to the |sum|); the factor measured on these workloads is below 3, so
+the bounds are 3u: 5.9e-3 (BF16) and 1.5e-3 (FP16).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import _problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BOUND = {1: 3 * 2.0 ** -9, 2: 3 * 2.0 ** -11}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - b).ravel()) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("name", ["axis32", "sphere45", "ragged44", "pct64"])
+@pytest.mark.parametrize("dtype", [1, 2], ids=["bf16", "fp16"])
+def test_mixed_precision_error_bounded(name, dtype):
+    from paper_2206_09151_amd import tomo
+    pb = _problems.make(name)
+    img = torch.from_numpy(pb.images).to("cuda:0")
+    ref = oracle.reconstruct(pb.images.astype(np.float64), pb.dirs, pb.dist, pb.oracle_geometry(), vaxes=pb.vaxes)
+    out = {}
+    for dt in (0, dtype):
+        plan = tomo.Plan(pb.params(angle_batch=7, plane_dtype=dt), pb.dirs, pb.dist, vaxes=pb.vaxes)
+        v = torch.empty((pb.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+        plan.reconstruct(img, v)
+        out[dt] = v.cpu().numpy().astype(np.float64)
+    e32, e16 = _rel(out[0], ref), _rel(out[dtype], ref)
+    print(f"{name} dtype={dtype}: rel-L2 vs FP64 = {e16:.3e} (FP32 path {e32:.3e})")
+    assert e32 < 1e-5
+    assert e16 < BOUND[dtype], e16
+    assert e16 > e32          # the reduced storage is what limits accuracy
+
+
+@pytest.mark.parametrize("dtype", [1, 2], ids=["bf16", "fp16"])
+def test_mixed_precision_stage_entry_points(dtype):
+    """backpropagate + grid with 16-bit stacks equals reconstruct bit for bit."""
+    from paper_2206_09151_amd import tomo
+    pb = _problems.make("ragged44")
+    plan = tomo.Plan(pb.params(angle_batch=5, plane_dtype=dtype), pb.dirs, pb.dist)
+    img = torch.from_numpy(pb.images).to("cuda:0")
+    full = torch.empty((pb.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+    plan.reconstruct(img, full)
+    acc = torch.zeros_like(full)
+    st = torch.empty(plan.stack_shape(5), dtype=plan.stack_dtype, device="cuda:0")
+    for first in range(0, pb.n, 5):
+        nb = min(5, pb.n - first)
+        plan.backpropagate(img[first:first + nb].contiguous(), first, nb, st)
+        plan.grid(st, first, nb, acc)
+    torch.cuda.synchronize()
+    assert torch.equal(acc, full)
