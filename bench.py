@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dt_ewald_128")
     ap.add_argument("--angle-batch", type=int, default=0)
+    ap.add_argument("--plane-dtype", default="f32", choices=["f32", "bf16", "fp16"],
+                    help="storage type of the plane stacks (interpolation and sums stay FP32)")
+    ap.add_argument("--cpu-voxels", type=int, default=0,
+                    help="evaluate the oracle sample at this many seeded voxels (0: all voxels)")
     ap.add_argument("--cpu-views", type=int, default=48, help="views in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -65,22 +69,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool) -> float:
-    """Compulsory HBM bytes of one launch over nb views."""
+def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool, sbytes: int = 4) -> float:
+    """Compulsory HBM bytes of one launch over nb views; sbytes = bytes
+    per stored plane value."""
     N, M, K = w.n_vox, w.M, w.K
     if kind == "spectra":   # image read + filter table read + Q write (16 B per coefficient each)
         return nb * (4.0 * M * M + 16.0 * M * M + 16.0 * M * M)
     if kind == "planes":    # Q read once per view + plane stack write
-        return nb * (16.0 * M * M + 4.0 * M * K * M)
+        return nb * (16.0 * M * M + sbytes * M * K * M)
     if kind == "grid":      # plane stack read + volume write (+ read when accumulating)
-        return nb * 4.0 * M * K * M + (4.0 if first_batch else 8.0) * N ** 3
+        return nb * sbytes * M * K * M + (4.0 if first_batch else 8.0) * N ** 3
     raise KeyError(kind)
 
 
-def read_traffic(kind: str, src_hash: str):
+def read_traffic(kind: str, src_hash: str, workload: str, storage: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kind}.json")
+    taken on the current kernel source for this workload and plane storage."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload}_{storage}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -115,7 +120,8 @@ def main():
     params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
                          sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in,
-                         angle_batch=args.angle_batch)
+                         angle_batch=args.angle_batch,
+                         plane_dtype={"f32": tomo.F32, "bf16": tomo.BF16, "fp16": tomo.F16}[args.plane_dtype])
     stream = torch.cuda.current_stream()
     plan = tomo.Plan(params, dirs, dist, stream=stream)
     batch = plan.batch
@@ -152,19 +158,25 @@ def main():
             if cnt == 0:
                 continue
             # bytes of all launches of one step (the first batch writes V without reading it)
-            step_bytes = sum(algorithmic_bytes(kind, w, min(batch, w.n_views - b * batch), b == 0)
-                             for b in range(n_batches))
+            sb = 4 if args.plane_dtype == "f32" else 2
+            if kind == "spectra":   # one launch over all views
+                step_bytes = algorithmic_bytes(kind, w, w.n_views, True, sb)
+                per_launch = step_bytes / cnt * args.steps
+            else:
+                step_bytes = sum(algorithmic_bytes(kind, w, min(batch, w.n_views - b * batch), b == 0, sb)
+                                 for b in range(n_batches))
+                per_launch = step_bytes / n_batches
             avg_ms = tot / cnt
             kernels[kind] = {"avg_ms": avg_ms, "launches_per_step": cnt / args.steps,
                              "ms_per_step": tot / args.steps,
-                             "algorithmic_bytes_per_launch": step_bytes / n_batches,
-                             "GBps": step_bytes / n_batches / (avg_ms * 1e-3) / 1e9}
+                             "algorithmic_bytes_per_launch": per_launch,
+                             "GBps": per_launch / (avg_ms * 1e-3) / 1e9}
         dom = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
         src_hash = kernel_source_hash()
         achieved = kernels[dom]["GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": read_traffic(dom, src_hash),
+                    "traffic": read_traffic(dom, src_hash, w.name, args.plane_dtype),
                     "ms_per_step_with_events": round(ms_timed, 4), "kernel_source_hash": src_hash}
         print(f"[bench] kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
@@ -177,12 +189,18 @@ def main():
         geo = oracle.Geometry(w.n_vox, w.M, w.K if w.ewald else 1, w.voxel, w.wavelength, w.sigma, w.epsilon,
                               ewald=w.ewald, weight_mode=w.weight_mode, eps_sampling=w.eps_sampling,
                               i_in=w.i_in)
+        vox = None
+        if args.cpu_voxels:
+            vox = np.random.default_rng(7).integers(0, w.n_vox, size=(args.cpu_voxels, 3))
         t = time.perf_counter()
-        ref = oracle.reconstruct_views(imgs.astype(np.float64), dirs, dist, geo, views=views)
+        ref = oracle.reconstruct_views(imgs.astype(np.float64), dirs, dist, geo, views=views, voxels=vox)
         cpu_s = time.perf_counter() - t
-        cpu = {"value": float(w.n_vox) ** 3 * nv / cpu_s, "unit": "voxel*angle updates/s", "cores": 1,
-               "kind": "oracle", "sample": f"{nv} of {w.n_views} views, full {w.n_vox}^3 volume, "
-                                           f"{cpu_s:.1f} s (numpy FP64, single thread)"}
+        nvox = w.n_vox ** 3 if vox is None else len(vox)
+        cpu = {"value": float(nvox) * nv / cpu_s, "unit": "voxel*angle updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": (f"{nv} of {w.n_views} views, " +
+                          (f"full {w.n_vox}^3 volume" if vox is None else f"{nvox} seeded voxels") +
+                          f", {cpu_s:.1f} s (numpy FP64, single thread; includes the plan-stage weights)")}
         # the same views through the HIP path (stage entry points), compared over all voxels
         part = torch.zeros_like(vol)
         st = torch.empty(plan.stack_shape(min(batch, nv)), dtype=torch.float32, device=dev)
@@ -192,6 +210,8 @@ def main():
             plan.grid(st, first, nb, part, stream=stream)
         torch.cuda.synchronize()
         got = part.cpu().numpy().astype(np.float64)
+        if vox is not None:
+            got = got[vox[:, 0], vox[:, 1], vox[:, 2]]
         rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         print(f"[bench] oracle {cpu_s:.1f}s on {nv} views; rel-L2 {rel_l2:.3g}", file=sys.stderr, flush=True)
 
@@ -209,6 +229,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n_vox": w.n_vox, "n_pix": w.M, "n_planes": w.K,
+                   "plane_storage": args.plane_dtype,
                    "n_views": w.n_views, "ewald": w.ewald, "weight_mode": w.weight_mode,
                    "angle_batch": batch, "updates_per_step": updates},
         "rel_l2_vs_fp64": rel_l2,

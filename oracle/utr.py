@@ -181,7 +181,7 @@ def sampling_matrix(u, v, d, geo: Geometry):
     s = np.zeros(n ** 3)
     for sign in (1.0, -1.0):
         for flat, wgt, ok in _trilinear_taps(sign * pts, n):
-            np.add.at(s, flat[ok], 0.5 * wgt[ok])
+            s += np.bincount(flat[ok], weights=0.5 * wgt[ok], minlength=n ** 3)
     return s.reshape(n, n, n)
 
 

@@ -26,6 +26,9 @@ struct tomo_plan_s {
   float2* d_prop = nullptr;     // [npairs][M]
   float2* d_tw_fwd = nullptr;   // [M]
   float2* d_tw_inv = nullptr;   // [M]
+  float2* d_tw2_fwd = nullptr;  // [M/2] twiddles of the half-size sub-transforms (M = 256)
+  float2* d_tw2_inv = nullptr;  // [M/2]
+  float* d_l1part = nullptr;    // [n][4] quadrant spectral bounds (M = 256, FP16)
   float4* d_q = nullptr;        // [n][M][M]  filtered spectra of every view
   void* d_stack = nullptr;      // [batch][M][K][M] of the plane storage type
   float* d_scale = nullptr;     // [n] FP16 plane scale per view (powers of two)
@@ -88,9 +91,10 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   } else {
     // automatic: about 128 MiB of stacks per batch (they stay in the 256 MB last-level
     // cache between the back-propagation and the gridding kernels), a multiple of 8
+    // and at least 8 views: the plane kernels put each view on one of the 8 XCDs
     const size_t target = size_t(128) << 20;
-    int b = int(std::max<size_t>(1, target / sv));
-    if (b >= 8) b -= b % 8;
+    int b = int(std::max<size_t>(8, target / sv));
+    b -= b % 8;
     r->batch = std::min(b, r->n);
   }
   r->table_bytes = size_t(r->n) * sizeof(ViewGeom) + size_t(r->n) * qv + size_t(r->npairs) * r->M * 8 +
@@ -102,7 +106,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
 std::string supported(const tomo_params* p, const Resolved& r) {
   if (!tomo::fft_supported(r.M)) {
     char b[160];
-    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128)", r.M);
+    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128, 256)", r.M);
     return b;
   }
   return "";
@@ -205,6 +209,9 @@ void free_plan(tomo_plan_s* pl) {
   (void)hipFree(pl->d_prop);
   (void)hipFree(pl->d_tw_fwd);
   (void)hipFree(pl->d_tw_inv);
+  (void)hipFree(pl->d_tw2_fwd);
+  (void)hipFree(pl->d_tw2_inv);
+  (void)hipFree(pl->d_l1part);
   (void)hipFree(pl->d_q);
   (void)hipFree(pl->d_stack);
   (void)hipFree(pl->d_scale);
@@ -338,6 +345,12 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
     twf[k] = make_float2(float(std::cos(a)), float(-std::sin(a)));
     twi[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
   }
+  std::vector<float2> tw2f(r.M / 2), tw2i(r.M / 2);
+  for (int k = 0; k < r.M / 2; ++k) {
+    const double a = 2.0 * kPi * k / (r.M / 2);
+    tw2f[k] = make_float2(float(std::cos(a)), float(-std::sin(a)));
+    tw2i[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
 
   hipError_t e = hipSuccess;
   const size_t mm = size_t(r.M) * r.M;
@@ -346,6 +359,9 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       (e = dev_alloc(&pl->d_prop, prop.size())) != hipSuccess ||
       (e = dev_alloc(&pl->d_tw_fwd, size_t(r.M))) != hipSuccess ||
       (e = dev_alloc(&pl->d_tw_inv, size_t(r.M))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_tw2_fwd, size_t(r.M / 2))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_tw2_inv, size_t(r.M / 2))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_l1part, size_t(4) * r.n)) != hipSuccess ||
       (e = dev_alloc(&pl->d_q, mm * r.n)) != hipSuccess ||
       (e = dev_alloc(reinterpret_cast<char**>(&pl->d_stack),
                      size_t(r.batch) * stack_view_bytes(r.M, r.K, p->plane_dtype))) != hipSuccess ||
@@ -373,6 +389,9 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       (e = hipMemcpyAsync(pl->d_prop, prop.data(), sizeof(float2) * prop.size(), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(pl->d_tw_fwd, twf.data(), sizeof(float2) * r.M, hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(pl->d_tw_inv, twi.data(), sizeof(float2) * r.M, hipMemcpyHostToDevice, s)) ||
+      (r.M / 2 > 0 &&
+       ((e = hipMemcpyAsync(pl->d_tw2_fwd, tw2f.data(), sizeof(float2) * (r.M / 2), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(pl->d_tw2_inv, tw2i.data(), sizeof(float2) * (r.M / 2), hipMemcpyHostToDevice, s)))) ||
       (e = hipMemsetAsync(pl->d_status, 0, sizeof(int), s)))
     return cleanup_fail(e, "upload");
 
@@ -425,7 +444,8 @@ static tomo_status run_spectra(tomo_plan_t pl, const float* d_images, int32_t fi
   float* scale = pl->p.plane_dtype == TOMO_F16 ? pl->d_scale + first : nullptr;
   hipError_t e = timed(pl, 0, s, [&] {
     return tomo::launch_spectra(pl->M, d_images, pl->d_filt + size_t(first) * mm, pl->d_tw_fwd,
-                                pl->d_q + size_t(first) * mm, pl->d_status, 1.0 / pl->p.i_in, scale, nb, s);
+                                pl->d_q + size_t(first) * mm, pl->d_status, 1.0 / pl->p.i_in, scale, nb, s,
+                                pl->d_tw2_fwd, pl->d_l1part + size_t(4) * first);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "spectra kernel");
   return TOMO_OK;
@@ -444,7 +464,7 @@ tomo_status tomo_backpropagate(tomo_plan_t pl, const float* d_images, int32_t fi
   const size_t mm = size_t(pl->M) * pl->M;
   hipError_t e = timed(pl, 1, s, [&] {
     return tomo::launch_planes(pl->M, pl->p.plane_dtype, pl->d_q + size_t(first) * mm, pl->d_prop, pl->d_tw_inv,
-                               d_planes, pl->K, pl->npairs, nb, pl->d_scale + first, s);
+                               d_planes, pl->K, pl->npairs, nb, pl->d_scale + first, s, pl->d_tw2_inv);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
   return TOMO_OK;
@@ -498,7 +518,8 @@ tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_vol
     const int nb = std::min(pl->batch, pl->n - first);
     hipError_t e = timed(pl, 1, s, [&] {
       return tomo::launch_planes(pl->M, pl->p.plane_dtype, pl->d_q + size_t(first) * mm, pl->d_prop,
-                                 pl->d_tw_inv, pl->d_stack, pl->K, pl->npairs, nb, pl->d_scale + first, s);
+                                 pl->d_tw_inv, pl->d_stack, pl->K, pl->npairs, nb, pl->d_scale + first, s,
+                                 pl->d_tw2_inv);
     });
     if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
     e = timed(pl, 2, s, [&] {

@@ -26,12 +26,16 @@ int fft_threads(int M);
 
 // g = ln(I/I_in) -> 2D DFT -> (G1 G, G2 G) for nb views.  filt, q: [nb][M][M] float4.
 // scale (FP16 planes only, else NULL): per-view power-of-two plane scale, [nb].
+// M = 256 also needs the 128-point twiddles (tw_half_fwd) and a [nb][4] scratch for the
+// quadrant bounds (l1part, FP16 only).
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
-                          float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s);
+                          float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
+                          const float2* tw_half_fwd, float* l1part);
 // Plane pairs (p, K-1-p), p < npairs, of nb views -> stack [nb][M][K][M] of dtype
 // (0 FP32, 1 BF16, 2 FP16 scaled by scale[view]).
 hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, const float2* tw_inv,
-                         void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s);
+                         void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s,
+                         const float2* tw_half_inv);
 // Trilinear gather of nb stacks into V[N][N][N] (accumulate: V += ..., else V = ...).
 // flat: one plane without depth axis (no Ewald curvature): bilinear in the detector plane.
 hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,

@@ -39,7 +39,7 @@ template <> struct Shape<128> : Fft2Shape<128, 16, 8> {};
 
 bool fft_supported(int M) {
   switch (M) {
-    case 16: case 32: case 48: case 64: case 80: case 96: case 128: return true;
+    case 16: case 32: case 48: case 64: case 80: case 96: case 128: case 256: return true;
     default: return false;
   }
 }
@@ -53,6 +53,7 @@ int fft_threads(int M) {
     case 80: return Shape<80>::T;
     case 96: return Shape<96>::T;
     case 128: return Shape<128>::T;
+    case 256: return Shape<128>::T;   // four 128-point quadrant transforms
     default: return 0;
   }
 }
@@ -202,6 +203,163 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
         const int xc = sg * S::E + e + S::R1 * k2;
         rowb[xc] = to_store<OutT>(x[e * S::R2 + k2].y * sc);
       }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ M = 256
+// A 256 x 256 block does not fit in one CU's LDS.  One radix-2 decimation in frequency
+// on both axes splits it into four independent 128 x 128 transforms:
+//   X[2k1+p1][2k2+p2] = DFT128_(n1,n2) { w^(p1 n1 + p2 n2) sum_{a,b} (-1)^(a p1 + b p2) x[n1+128a][n2+128b] }
+// with w = exp(-+ i 2 pi / 256).  Each (p1, p2) quadrant is one workgroup running the
+// 128 x 128 LDS transform; it reads its inputs from all four input quadrants and writes
+// every second output row and column.  The four workgroups of a block share an XCD.
+using Half256 = Shape<128>;
+
+// g = ln(I/I_in) of a 256 x 256 image -> filtered spectra (Q1, Q2) at the quadrant's
+// output positions; l1part[view][quad] = partial spectral bound for the FP16 scale.
+__global__ __launch_bounds__(1024) void k_spectra256(const float* __restrict__ images,
+                                                     const float4* __restrict__ filt,
+                                                     const float2* __restrict__ tw256,
+                                                     const float2* __restrict__ tw128,
+                                                     float4* __restrict__ q, int* __restrict__ status,
+                                                     double inv_iin, float* __restrict__ l1part) {
+  using S = Half256;
+  constexpr int M = 256, H = 128;
+  __shared__ float2 lds[(S::LDS_SPLIT_FLOATS + 1) / 2];
+  __shared__ float red[S::T / 64];
+  const int t = threadIdx.x;
+  const int view = blockIdx.x >> 2, quad = blockIdx.x & 3;
+  const int p1 = quad >> 1, p2 = quad & 1;
+  const int n2 = t % H;
+  const int r = __builtin_amdgcn_readfirstlane(t / H);
+  const float* img = images + size_t(view) * M * M;
+  float2 x[S::R1];
+  int bad = 0;
+#pragma unroll
+  for (int m = 0; m < S::R1; ++m) {
+    const int n1 = r + S::R2 * m;
+    float acc = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const float iv = img[(n1 + H * a) * M + n2 + H * b];
+        const bool ok = (iv > 0.0f) && (iv < INFINITY);
+        bad |= !ok;
+        const float g = ok ? float(log(double(iv) * inv_iin)) : 0.0f;
+        acc += ((a & p1) ^ (b & p2)) ? -g : g;
+      }
+    }
+    x[m] = cscale(tw256[(p1 * n1 + p2 * n2) & (M - 1)], acc);
+  }
+  if (bad) atomicOr(status, 1);
+  fft2_block_split<S, false>(x, reinterpret_cast<float*>(lds), tw128);
+  const int sg = t % S::R2, yy = t / S::R2;
+  const int ky = 2 * yy + p1;
+  const size_t row = (size_t(view) * M + ky) * M;
+  float l1 = 0.0f;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) {
+#pragma unroll
+    for (int k2 = 0; k2 < S::R2; ++k2) {
+      const int kx = 2 * (sg * S::E + e + S::R1 * k2) + p2;
+      const float4 f = filt[row + kx];
+      const float2 gg = x[e * S::R2 + k2];
+      float4 o;
+      o.x = f.x * gg.x - f.y * gg.y;
+      o.y = f.x * gg.y + f.y * gg.x;
+      o.z = f.z * gg.x - f.w * gg.y;
+      o.w = f.z * gg.y + f.w * gg.x;
+      q[row + kx] = o;
+      l1 += fabsf(o.x) + fabsf(o.y) + fabsf(o.z) + fabsf(o.w);
+    }
+  }
+  if (l1part) {
+    for (int off = 32; off > 0; off >>= 1) l1 += __shfl_xor(l1, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = l1;
+    __syncthreads();
+    if (t == 0) {
+      float tot = 0.0f;
+      for (int w = 0; w < S::T / 64; ++w) tot += red[w];
+      l1part[blockIdx.x] = tot;
+    }
+  }
+}
+
+// FP16 plane scale of each view from its four quadrant bounds (fixed summation order).
+__global__ void k_scale4(const float* __restrict__ l1part, float* __restrict__ scale, int nb) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nb) return;
+  const float tot = ((l1part[4 * v] + l1part[4 * v + 1]) + l1part[4 * v + 2]) + l1part[4 * v + 3];
+  scale[v] = tot > 0.0f ? exp2f(14.0f - ceilf(log2f(tot))) : 1.0f;
+}
+
+// Plane pairs of 256 x 256 spectra: workgroup (view, pair, quadrant).
+template <class OutT>
+__global__ __launch_bounds__(1024) void k_planes256(const float4* __restrict__ q,
+                                                    const float2* __restrict__ prop,
+                                                    const float2* __restrict__ tw256,
+                                                    const float2* __restrict__ tw128,
+                                                    OutT* __restrict__ stack, int K, int npairs, int nb,
+                                                    const float* __restrict__ scale) {
+  using S = Half256;
+  constexpr int M = 256, H = 128;
+  __shared__ float2 lds[(S::LDS_SPLIT_FLOATS + 1) / 2];
+  const int wg = blockIdx.x;
+  const int xcd = wg & 7, k = wg >> 3;
+  const int per_view = npairs * 4;
+  const int view = xcd + 8 * (k / per_view);
+  const int rem = k % per_view;
+  const int p = rem >> 2, quad = rem & 3;
+  if (view >= nb) return;   // whole workgroup leaves together
+  const int p1 = quad >> 1, p2 = quad & 1;
+  const int t = threadIdx.x;
+  const int n2 = t % H;
+  const int r = __builtin_amdgcn_readfirstlane(t / H);
+  const float4* qv = q + size_t(view) * M * M;
+  const float2* pr = prop + size_t(p) * M;
+  const float2 cx0 = pr[n2], cx1 = pr[n2 + H];
+  float2 x[S::R1];
+#pragma unroll
+  for (int m = 0; m < S::R1; ++m) {
+    const int n1 = r + S::R2 * m;
+    float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const float2 cy = pr[n1 + H * a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const float2 cx = b ? cx1 : cx0;
+        const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+        const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+        const float4 qq = qv[(n1 + H * a) * M + n2 + H * b];
+        const float zr = c * qq.x + sn * qq.z, zi = c * qq.y + sn * qq.w;
+        if ((a & p1) ^ (b & p2)) {
+          acc.x -= zr;
+          acc.y -= zi;
+        } else {
+          acc.x += zr;
+          acc.y += zi;
+        }
+      }
+    }
+    x[m] = cmul(acc, tw256[(p1 * n1 + p2 * n2) & (M - 1)]);
+  }
+  fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw128);
+  const int sg = t % S::R2, yy = t / S::R2;
+  const int y = 2 * yy + p1;
+  const int pa = p, pb = K - 1 - p;
+  const float sc = scale ? scale[view] : 1.0f;
+  OutT* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
+  OutT* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
+#pragma unroll
+  for (int k2 = 0; k2 < S::R2; ++k2) {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) {
+      const int xc = 2 * (sg * S::E + e + S::R1 * k2) + p2;
+      rowa[xc] = to_store<OutT>(x[e * S::R2 + k2].x * sc);
+      if (pb != pa) rowb[xc] = to_store<OutT>(x[e * S::R2 + k2].y * sc);
     }
   }
 }
@@ -395,6 +553,198 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
         const float* r0 = &box[j][lp][lc];
         const float* r1 = &box[j][lp1][lc];
         acc[j] += w00 * r0[0] + w01 * r0[1] + w10 * r1[0] + w11 * r1[1];
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int j = 0; j < YB; ++j) {
+    const int iy = y0 + j;
+    if (iy < N) {
+      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
+      *dst = accumulate ? *dst + acc[j] : acc[j];
+    }
+  }
+}
+
+// General view frames with a compact footprint (e.g. single-axis scans with a tilt):
+// per view the bounding box of the workgroup's 16 (x) x YB (y) x 16 (z) voxel tile in
+// (row, plane, column) coordinates is staged into LDS when it fits in BR x 24 x BOXW;
+// the eight trilinear taps are then LDS reads.  Views whose box does not fit (steep
+// tilts, directions far from the rotation axis) are gathered from global memory.
+constexpr int BX_BR = 12;       // detector rows staged per view
+
+template <int YB, class InT>
+__global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
+                                                  const ViewGeom* __restrict__ geom,
+                                                  const float* __restrict__ scale,
+                                                  float* __restrict__ vol, int N, int M, int K,
+                                                  int nb, int accumulate, int flat) {
+  using B = AxisBox<InT>;
+  constexpr int VEC = B::VEC, BOXW = B::BOXW, BOXP = B::BOXP;
+  constexpr int BR = BX_BR, BH = AX_BOXH;
+  constexpr int QN = BOXW / VEC;
+  constexpr int NE = BR * BH * QN;
+  constexpr int PER = (NE + 255) / 256;
+  __shared__ float box[BR][BH][BOXP];
+  const int ntx = (N + GT - 1) / GT;
+  const int tiles = ntx * ntx;
+  const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
+  const int yblk = xcd + 8 * (k / tiles), tile = k % tiles;
+  const int y0 = yblk * YB;
+  if (y0 >= N) return;                                  // uniform
+  const int tx0 = (tile % ntx) * GT, tz0 = (tile / ntx) * GT;
+  const int ix = tx0 + (threadIdx.x % GT);
+  const int iz = tz0 + (threadIdx.x / GT);
+  const bool live = ix < N && iz < N;
+  const double c = 0.5 * (N - 1);
+  const double rx = ix - c, rz = iz - c;
+  const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
+  const size_t plane_sz = size_t(K) * M;
+  const bool vec = (M % VEC) == 0;
+  const double lo[3] = {tx0 - c, y0 - c, tz0 - c};
+  const double hi[3] = {tx0 + GT - 1 - c, y0 + YB - 1 - c, tz0 + GT - 1 - c};
+
+  // box of view n: origin (r0, p0, c0) and whether it fits (uniform)
+  auto origin = [&](int n, int& r0, int& p0, int& c0) -> bool {
+    const ViewGeom& g = geom[n];
+    double cmin = hm, cmax = hm, rmin = hm, rmax = hm, pmin = hk, pmax = hk;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cmin += fmin(g.u[a] * lo[a], g.u[a] * hi[a]);
+      cmax += fmax(g.u[a] * lo[a], g.u[a] * hi[a]);
+      rmin += fmin(g.v[a] * lo[a], g.v[a] * hi[a]);
+      rmax += fmax(g.v[a] * lo[a], g.v[a] * hi[a]);
+      pmin += fmin(g.d[a] * lo[a], g.d[a] * hi[a]);
+      pmax += fmax(g.d[a] * lo[a], g.d[a] * hi[a]);
+    }
+    c0 = int(floor(cmin)) & ~(VEC - 1);
+    r0 = int(floor(rmin));
+    p0 = flat ? 0 : int(floor(pmin));
+    // taps reach floor(max)+1; keep one slot of slack for rounding
+    return vec && (int(floor(cmax)) + 2 - c0 < BOXW) && (int(floor(rmax)) + 2 - r0 < BR) &&
+           (flat || int(floor(pmax)) + 2 - p0 < BH);
+  };
+  auto fetch = [&](int n, int r0, int p0, int c0, uint4 (&v)[PER], unsigned& valid) {
+    const InT* vbase = stack + size_t(n) * plane_sz * M;
+    valid = 0u;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int q = e % QN, pl = (e / QN) % BH, j = e / (QN * BH);
+      const int row = r0 + j, pp = p0 + pl, cc = c0 + VEC * q;
+      const bool ok = e < NE && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) && cc >= 0 && cc < M &&
+                      vec;
+      valid |= ok ? (1u << i) : 0u;
+      const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
+      const int ccc = min(max(cc, 0), M - VEC);
+      v[i] = *reinterpret_cast<const uint4*>(stack + size_t(n) * plane_sz * M + (size_t(rowc) * K + ppc) * M +
+                                             (vec ? ccc : 0));
+      (void)vbase;
+    }
+  };
+  auto stage = [&](const uint4 (&v)[PER], unsigned valid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NE) {
+        const int q = e % QN, pl = (e / QN) % BH, j = e / (QN * BH);
+        Chunk16 x;
+        x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
+        float* dst = &box[j][pl][VEC * q];
+#pragma unroll
+        for (int h = 0; h < VEC; h += 4)
+          *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
+                                                            chunk_value<InT>(x, h + 2), chunk_value<InT>(x, h + 3));
+      }
+    }
+  };
+
+  float acc[YB];
+#pragma unroll
+  for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
+  uint4 buf[PER];
+  unsigned valid = 0u;
+  int r0 = 0, p0 = 0, c0 = 0;
+  bool fits = false;
+  if (nb > 0) {
+    fits = origin(0, r0, p0, c0);
+    if (fits) fetch(0, r0, p0, c0, buf, valid);
+  }
+  for (int n = 0; n < nb; ++n) {
+    const bool fits_n = fits;
+    const int rr0 = r0, pp0 = p0, cc0 = c0;
+    __syncthreads();                                    // previous view's LDS reads are done
+    if (fits_n) stage(buf, valid);
+    __syncthreads();
+    if (n + 1 < nb) {                                   // next view's loads overlap this view's math
+      fits = origin(n + 1, r0, p0, c0);
+      if (fits) fetch(n + 1, r0, p0, c0, buf, valid);
+    }
+    if (!live) continue;
+    const ViewGeom& g = geom[n];
+    const float inv = scale ? 1.0f / scale[n] : 1.0f;   // exact: the scale is a power of two
+    const double bc = g.u[0] * rx + g.u[2] * rz + hm;
+    const double br = g.v[0] * rx + g.v[2] * rz + hm;
+    const double bp = g.d[0] * rx + g.d[2] * rz + hk;
+    if (fits_n) {
+      // box-local coordinates of the thread's first voxel row in FP64, rounded once; the
+      // other rows step by (u_y, v_y, d_y) in FP32 (|local| < 32: error ~1e-6 voxel)
+      const double ry0 = y0 - c;
+      const float lc0 = float(g.u[1] * ry0 + bc - cc0), lr0 = float(g.v[1] * ry0 + br - rr0);
+      const float lp0 = flat ? 0.0f : float(g.d[1] * ry0 + bp - pp0);
+      const float uy = float(g.u[1]), vy = float(g.v[1]), dy = flat ? 0.0f : float(g.d[1]);
+#pragma unroll
+      for (int j = 0; j < YB; ++j) {
+        // fmax guards against a rounding-level dip below the box origin
+        const float fc = fmaxf(fmaf(float(j), uy, lc0), 0.0f);
+        const float fr = fmaxf(fmaf(float(j), vy, lr0), 0.0f);
+        const float fp = fmaxf(fmaf(float(j), dy, lp0), 0.0f);
+        const float fc0 = floorf(fc), fr0 = floorf(fr), fp0 = floorf(fp);
+        const float tc = fc - fc0, tr = fr - fr0, tp = fp - fp0;
+        const int lc = int(fc0), lr = int(fr0), lp = int(fp0);
+        const int lp1 = flat ? lp : lp + 1;
+        const float* a0 = &box[lr][lp][lc];
+        const float* a1 = &box[lr][lp1][lc];
+        const float* b0 = &box[lr + 1][lp][lc];
+        const float* b1 = &box[lr + 1][lp1][lc];
+        const float wp1 = flat ? 0.0f : tp, wp0 = 1.0f - wp1;
+        const float v0 = a0[0] + tc * (a0[1] - a0[0]);
+        const float v1 = a1[0] + tc * (a1[1] - a1[0]);
+        const float v2 = b0[0] + tc * (b0[1] - b0[0]);
+        const float v3 = b1[0] + tc * (b1[1] - b1[0]);
+        acc[j] += inv * ((1.0f - tr) * (wp0 * v0 + wp1 * v1) + tr * (wp0 * v2 + wp1 * v3));
+      }
+    } else {
+      const InT* base = stack + size_t(n) * plane_sz * M;
+      // one voxel row per iteration (rare path: keep its registers small)
+#pragma unroll 1
+      for (int j = 0; j < YB; ++j) {
+        const double ry = (y0 + j) - c;
+        const double fc = g.u[1] * ry + bc, fr = g.v[1] * ry + br, fp = g.d[1] * ry + bp;
+        const double fc0 = floor(fc), fr0 = floor(fr), fp0 = floor(fp);
+        const float tc = float(fc - fc0), tr = float(fr - fr0), tp = float(fp - fp0);
+        const int c0i = int(fc0), r0i = int(fr0), p0i = int(fp0);
+        const float wc0 = (unsigned(c0i) < unsigned(M)) ? 1.0f - tc : 0.0f;
+        const float wc1 = (unsigned(c0i + 1) < unsigned(M)) ? tc : 0.0f;
+        const float wr0 = (unsigned(r0i) < unsigned(M)) ? 1.0f - tr : 0.0f;
+        const float wr1 = (unsigned(r0i + 1) < unsigned(M)) ? tr : 0.0f;
+        const float wp0 = flat ? 1.0f : (unsigned(p0i) < unsigned(K)) ? 1.0f - tp : 0.0f;
+        const float wp1 = flat ? 0.0f : (unsigned(p0i + 1) < unsigned(K)) ? tp : 0.0f;
+        const int c0c = min(max(c0i, 0), M - 1), c1c = min(max(c0i + 1, 0), M - 1);
+        const int r0c = min(max(r0i, 0), M - 1), r1c = min(max(r0i + 1, 0), M - 1);
+        const int p0c = flat ? 0 : min(max(p0i, 0), K - 1), p1c = flat ? 0 : min(max(p0i + 1, 0), K - 1);
+        const InT* a0 = base + (size_t(r0c) * K + p0c) * M;
+        const InT* a1 = base + (size_t(r0c) * K + p1c) * M;
+        const InT* b0 = base + (size_t(r1c) * K + p0c) * M;
+        const InT* b1 = base + (size_t(r1c) * K + p1c) * M;
+        const float v0 = wc0 * from_store<InT>(a0[c0c]) + wc1 * from_store<InT>(a0[c1c]);
+        const float v1 = wc0 * from_store<InT>(a1[c0c]) + wc1 * from_store<InT>(a1[c1c]);
+        const float v2 = wc0 * from_store<InT>(b0[c0c]) + wc1 * from_store<InT>(b0[c1c]);
+        const float v3 = wc0 * from_store<InT>(b1[c0c]) + wc1 * from_store<InT>(b1[c1c]);
+        const float add = inv * (wr0 * (wp0 * v0 + wp1 * v1) + wr1 * (wp0 * v2 + wp1 * v3));
+#pragma unroll
+        for (int jj = 0; jj < YB; ++jj) acc[jj] += (jj == j) ? add : 0.0f;
       }
     }
   }
@@ -642,16 +992,44 @@ static hipError_t planes_dtype(int dtype, const float4* q, const float2* prop, c
   }
 
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
-                          float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s) {
+                          float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
+                          const float2* tw_half_fwd, float* l1part) {
   if (nb <= 0) return hipSuccess;
+  if (M == 256) {
+    hipLaunchKernelGGL(k_spectra256, dim3(4 * nb), dim3(Half256::T), 0, s, images, filt, tw_fwd, tw_half_fwd, q,
+                       status, inv_iin, scale ? l1part : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !scale) return e;
+    hipLaunchKernelGGL(k_scale4, dim3((nb + 255) / 256), dim3(256), 0, s, l1part, scale, nb);
+    return hipGetLastError();
+  }
 #define CALL(MM) spectra_impl<MM>(images, filt, tw_fwd, q, status, inv_iin, scale, nb, s)
   TOMO_DISPATCH_M(M, CALL)
 #undef CALL
 }
 
+template <class OutT>
+static hipError_t planes256_impl(const float4* q, const float2* prop, const float2* tw256, const float2* tw128,
+                                 void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s) {
+  const int nb8 = (nb + 7) / 8;
+  hipLaunchKernelGGL(k_planes256<OutT>, dim3(8 * 4 * npairs * nb8), dim3(Half256::T), 0, s, q, prop, tw256, tw128,
+                     static_cast<OutT*>(stack), K, npairs, nb, scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, const float2* tw_inv,
-                         void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s) {
+                         void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s,
+                         const float2* tw_half_inv) {
   if (nb <= 0) return hipSuccess;
+  if (M == 256) {
+    switch (dtype) {
+      case 0: return planes256_impl<float>(q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, nullptr, s);
+      case 1:
+        return planes256_impl<__hip_bfloat16>(q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, nullptr, s);
+      case 2: return planes256_impl<__half>(q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
 #define CALL(MM) planes_dtype<MM>(dtype, q, prop, tw_inv, stack, K, npairs, nb, scale, s)
   TOMO_DISPATCH_M(M, CALL)
 #undef CALL
@@ -671,8 +1049,10 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
     hipLaunchKernelGGL((k_grid_axis<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
                        scale, vol, N, M, K, nb, accumulate, flat);
   } else {
-    hipLaunchKernelGGL((k_grid_gen<kYB, InT>), grid, dim3(256), 0, s, st, geom, scale, vol, N, M, K, nb,
-                       accumulate, flat);
+    const int tiles = int(grid.x * grid.y);
+    const int yblocks8 = int((grid.z + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_grid_box<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
+                       scale, vol, N, M, K, nb, accumulate, flat);
   }
   return hipGetLastError();
 }

@@ -121,7 +121,24 @@ def make(name: str) -> Problem:
         lam, sig = 0.1e-10, 0.3
         imgs = _born(19, N, M, dx, lam, dirs, dist, sig)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs, vaxes=vax)
+    if name == "m256":
+        # 256-pixel detector (quadrant-split FFT path) over a small volume, single axis
+        n, N, M, K = 6, 48, 256, 48
+        dirs = scan.single_axis(n, 180.0, offset_deg=11.0)
+        dist = np.full(n, 80e-10)
+        lam, sig = 0.05e-10, -0.1
+        imgs = _born(20, N, M, dx, lam, dirs, dist, sig, count=30)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "m256sph":
+        # 256-pixel detector, directions on the sphere (general trilinear path), odd K
+        n, N, M, K = 5, 40, 256, 41
+        dirs = scan.uniform_sphere(21, n)
+        dist = np.full(n, 80e-10)
+        lam, sig = 0.05e-10, 0.2
+        imgs = _born(21, N, M, dx, lam, dirs, dist, sig, count=30)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
     raise KeyError(name)
 
 
-SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32"]
+SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32",
+         "m256", "m256sph"]
