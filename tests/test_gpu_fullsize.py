@@ -35,3 +35,45 @@ def test_dt_ewald_128_sampled_voxels_match_oracle():
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     assert rel < 1e-5, rel
     assert np.isfinite(got).all()
+
+
+@pytest.fixture(scope="module")
+def xray_case():
+    """The 256^3, 360-view X-ray workload and the oracle's partial sum over one launch
+    batch of 8 views (first = 100) at 3000 seeded voxels, computed once."""
+    from synth import workloads
+    w = workloads.WORKLOADS["xray_jitter_256"]
+    ph, dirs, dist, imgs64 = workloads.make_workload(w, device="cuda")
+    imgs = imgs64.astype(np.float32)
+    first, nb = 100, 8
+    vox = np.random.default_rng(11).integers(0, w.n_vox, size=(3000, 3))
+    geo = oracle.Geometry(w.n_vox, w.M, w.K, w.voxel, w.wavelength, w.sigma, w.epsilon, ewald=w.ewald,
+                          weight_mode=w.weight_mode)
+    ref = oracle.reconstruct_views(imgs.astype(np.float64), dirs, dist, geo, views=np.arange(first, first + nb),
+                                   voxels=vox)
+    return w, dirs, dist, imgs, first, nb, vox, ref
+
+
+@pytest.mark.parametrize("storage,bound", [(0, 1e-5), (1, 3 * 2.0 ** -9), (2, 3 * 2.0 ** -11)],
+                         ids=["f32", "bf16", "fp16"])
+def test_xray_jitter_256_view_batch_matches_oracle(xray_case, storage, bound):
+    """Full size, +-5 deg tilt jitter, sampling-matrix weights from all 360 directions on
+    both sides: one launch batch of 8 views through the stage entry points (the kernels
+    and launch shapes tomo_reconstruct uses), compared at 3000 seeded voxels."""
+    from paper_2206_09151_amd import tomo
+    w, dirs, dist, imgs, first, nb, vox, ref = xray_case
+    params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
+                         sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
+                         weight_mode=w.weight_mode, plane_dtype=storage)
+    plan = tomo.Plan(params, dirs, dist)
+    assert plan.batch == nb
+    d_img = torch.from_numpy(imgs[first:first + nb]).to("cuda:0")
+    st = torch.empty(plan.stack_shape(nb), dtype=plan.stack_dtype, device="cuda:0")
+    vol = torch.zeros((w.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+    plan.backpropagate(d_img, first, nb, st)
+    plan.grid(st, first, nb, vol)
+    got = vol.cpu().numpy()
+    g = got[vox[:, 0], vox[:, 1], vox[:, 2]].astype(np.float64)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    print(f"xray_jitter_256 storage={storage}: rel-L2 vs FP64 = {rel:.3e}")
+    assert rel < bound, rel
