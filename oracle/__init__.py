@@ -5,4 +5,7 @@ Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg of
 shares no code with the HIP path.
 """
 from .utr import *  # noqa: F401,F403
-from .utr import __all__  # noqa: F401
+from .fourier import *  # noqa: F401,F403
+from . import utr as _utr, fourier as _fourier
+
+__all__ = list(_utr.__all__) + list(_fourier.__all__)

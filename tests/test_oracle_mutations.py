@@ -79,3 +79,85 @@ def test_planted_mistake_is_caught(monkeypatch, name, bad, pin):
         monkeypatch.setattr(oracle, name, bad)
     with pytest.raises(AssertionError):
         pin()
+
+
+# ------------------------------------------------------------------ Fourier-space form
+import oracle.fourier as fou  # noqa: E402
+import test_oracle_fourier as fpins  # noqa: E402
+
+
+def _spectra_no_centring(images, geo):
+    return utr.spectrum(utr.contrast(images, geo.i_in))
+
+
+def _grid_no_conjugate(values, u, v, d, geo):
+    n = geo.n_vox
+    pts = utr._paraboloid_points(u, v, d, geo).reshape(-1, 3)
+    val = np.asarray(values).reshape(-1)
+    F = np.zeros(n ** 3, dtype=complex)
+    S = np.zeros(n ** 3)
+    for sign in (1.0, -1.0):
+        for flat, wgt, ok in utr._trilinear_taps(sign * pts, n):
+            np.add.at(F, flat[ok], 0.5 * wgt[ok] * val[ok])        # reflection not conjugated
+            np.add.at(S, flat[ok], 0.5 * wgt[ok])
+    return F.reshape(n, n, n), S.reshape(n, n, n)
+
+
+_orig_inverse = fou.inverse_dft3
+
+
+def _inverse_xy_swapped(A, geo):
+    return np.swapaxes(_orig_inverse(A, geo), 1, 2)
+
+
+def _normalise_by_s_squared(F, S, geo, nsr=0.0):
+    A = F / (S * S + geo.eps_sampling)
+    if nsr > 0:
+        thr = np.where(S > 0, nsr * geo.n_pix / np.sqrt(np.maximum(S, 1e-300)), np.inf)
+        A = np.where(np.abs(A) >= thr, A, 0.0)
+    return A
+
+
+def _nsr_over_s(F, S, geo, nsr=0.0):
+    A = F * S / (S * S + geo.eps_sampling)
+    if nsr > 0:
+        thr = np.where(S > 0, nsr * geo.n_pix / np.maximum(S, 1e-300), np.inf)   # S, not sqrt(S)
+        A = np.where(np.abs(A) >= thr, A, 0.0)
+    return A
+
+
+def _paraboloid_flipped(u, v, d, geo):
+    m = geo.n_pix
+    q = utr.signed_index(m) / (m * geo.voxel)
+    qy, qx = np.meshgrid(q, q, indexing="ij")
+    qz = +geo.ewald * geo.wavelength * (qx ** 2 + qy ** 2) / 2.0                 # wrong sign
+    p = (qx[None, :, :, None] * u[:, None, None, :] + qy[None, :, :, None] * v[:, None, None, :]
+         + qz[None, :, :, None] * d[:, None, None, :])
+    return p * (geo.n_vox * geo.voxel)
+
+
+def _inverse_no_pixel_area(A, geo):
+    return _orig_inverse(A, geo) / geo.voxel ** 2
+
+
+def _single_view_even():
+    fpins.test_single_view_on_grid_reduces_to_2d_inverse_dft(16, 11)
+
+
+FOURIER_MUTATIONS = [
+    ("centred_spectra", _spectra_no_centring, _single_view_even),
+    ("fourier_grid", _grid_no_conjugate, _single_view_even),
+    ("inverse_dft3", _inverse_xy_swapped, _single_view_even),
+    ("inverse_dft3", _inverse_no_pixel_area, _single_view_even),
+    ("fourier_normalise", _normalise_by_s_squared, fpins.test_nsr_threshold_scales_with_inverse_sqrt_of_sampling),
+    ("fourier_normalise", _nsr_over_s, fpins.test_nsr_threshold_scales_with_inverse_sqrt_of_sampling),
+    ("_paraboloid_points", _paraboloid_flipped, fpins.test_fourier_form_needs_curvature_when_dof_is_small),
+]
+
+
+@pytest.mark.parametrize("name,bad,pin", FOURIER_MUTATIONS,
+                         ids=[f"{m[0]}-{m[1].__name__}" for m in FOURIER_MUTATIONS])
+def test_planted_fourier_mistake_is_caught(monkeypatch, name, bad, pin):
+    monkeypatch.setattr(fou, name, bad)
+    with pytest.raises(AssertionError):
+        pin()
