@@ -1,10 +1,14 @@
 """Throughput of the DT back-propagation + gridding hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dt_ewald_128]
+                    [--method realspace|fourier [--variant 11|12] [--nsr X]]
 
 One step = one full reconstruction (all views: contrast, DFT, eq. 11 filter,
 propagation to every depth plane, inverse FFTs, trilinear gridding) of the
-workload, images already resident in HBM.  Prints one JSON line.
+workload, images already resident in HBM.  Prints one JSON line.  With
+--method fourier a step is one reconstruction by the Fourier-space form instead
+(spectra, 3D gridding of the filtered spectra, normalisation, inverse 3D FFT);
+its throughput is quoted in the same unit (voxel*angle updates of the volume).
 
 The roofline object is computed for the kernel with the largest share of the
 step, from library-side HIP event timing (two events around every launch, on
@@ -41,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-voxels", type=int, default=0,
                     help="evaluate the oracle sample at this many seeded voxels (0: all voxels)")
     ap.add_argument("--cpu-views", type=int, default=48, help="views in the oracle sample")
+    ap.add_argument("--method", default="realspace", choices=["realspace", "fourier"])
+    ap.add_argument("--variant", type=int, default=11, choices=[11, 12], help="Fourier-space form: eq. 11 or 12")
+    ap.add_argument("--nsr", type=float, default=0.0, help="Fourier-space noise filter level (0: off)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -70,9 +77,14 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool, sbytes: int = 4) -> float:
-    """Compulsory HBM bytes of one launch over nb views; sbytes = bytes
-    per stored plane value."""
+    """Compulsory HBM bytes of one launch over nb views; sbytes = bytes per stored
+    plane value."""
     N, M, K = w.n_vox, w.M, w.K
+    P = N + (1 - N % 2)
+    if kind == "fsplat":    # filtered spectra read + accumulator written once (clear) and updated once
+        return nb * 16.0 * M * M + 2 * 16.0 * P ** 3
+    if kind == "finverse":  # accumulator + S read, complex grid written, 3 FFT passes, volume written
+        return 16.0 * P ** 3 + 8.0 * N ** 3 + 8.0 * N ** 3 + 2 * 2 * 8.0 * N ** 3 + 8.0 * N ** 3 + 4.0 * N ** 3
     if kind == "spectra":   # image read + filter table read + Q write (16 B per coefficient each)
         return nb * (4.0 * M * M + 16.0 * M * M + 16.0 * M * M)
     if kind == "planes":    # Q read once per view + plane stack write
@@ -120,18 +132,25 @@ def main():
     params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
                          sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in,
-                         angle_batch=args.angle_batch,
+                         angle_batch=args.angle_batch, fourier=1 if args.method == "fourier" else 0,
                          plane_dtype={"f32": tomo.F32, "bf16": tomo.BF16, "fp16": tomo.F16}[args.plane_dtype])
     stream = torch.cuda.current_stream()
     plan = tomo.Plan(params, dirs, dist, stream=stream)
     batch = plan.batch
+    fourier = args.method == "fourier"
+
+    def step():
+        if fourier:
+            plan.fourier_reconstruct(d_img, vol, variant=args.variant, nsr=args.nsr, stream=stream)
+        else:
+            plan.reconstruct(d_img, vol, stream=stream)
 
     for _ in range(args.warmup):
-        plan.reconstruct(d_img, vol, stream=stream)
+        step()
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(args.steps):
-        plan.reconstruct(d_img, vol, stream=stream)
+        step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     ms = elapsed * 1e3 / args.steps
@@ -147,7 +166,7 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
-            plan.reconstruct(d_img, vol, stream=stream)
+            step()
         torch.cuda.synchronize()
         ms_timed = (time.perf_counter() - t) * 1e3 / args.steps
         plan.timing(False)
@@ -159,7 +178,7 @@ def main():
                 continue
             # bytes of all launches of one step (the first batch writes V without reading it)
             sb = 4 if args.plane_dtype == "f32" else 2
-            if kind == "spectra":   # one launch over all views
+            if kind == "spectra" or fourier:   # one launch over all views per step
                 step_bytes = algorithmic_bytes(kind, w, w.n_views, True, sb)
                 per_launch = step_bytes / cnt * args.steps
             else:
@@ -182,7 +201,26 @@ def main():
 
     cpu = None
     rel_l2 = None
-    if not args.no_cpu:
+    if not args.no_cpu and fourier:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        geo = oracle.Geometry(w.n_vox, w.M, w.K if w.ewald else 1, w.voxel, w.wavelength, w.sigma, w.epsilon,
+                              ewald=w.ewald, weight_mode=w.weight_mode, eps_sampling=w.eps_sampling,
+                              i_in=w.i_in)
+        with threadpool_limits(1):
+            t = time.perf_counter()
+            ref = oracle.fourier_reconstruct(imgs.astype(np.float64), dirs, dist, geo, nsr=args.nsr,
+                                             variant=args.variant)
+            cpu_s = time.perf_counter() - t
+        cpu = {"value": updates / cpu_s, "unit": "voxel*angle updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"whole workload ({w.n_views} views, {w.n_vox}^3), {cpu_s:.1f} s "
+                         "(numpy FP64 Fourier-space form, one thread)"}
+        plan.fourier_reconstruct(d_img, vol, variant=args.variant, nsr=args.nsr, stream=stream)
+        torch.cuda.synchronize()
+        got = vol.cpu().numpy().astype(np.float64)
+        rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"[bench] oracle {cpu_s:.1f}s; rel-L2 {rel_l2:.3g}", file=sys.stderr, flush=True)
+    elif not args.no_cpu:
         import oracle
         nv = min(args.cpu_views, w.n_views)
         views = np.arange(nv)
@@ -217,6 +255,7 @@ def main():
 
     out = {
         "metric": "voxel*angle updates/s (DT backprop+gridding)",
+        "method": args.method if not fourier else f"fourier_eq{args.variant}",
         "value": value,
         "unit": "voxel*angle updates/s",
         "n_gpus": 1,

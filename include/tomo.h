@@ -96,6 +96,8 @@ typedef struct {
   int32_t weight_mode;    /* tomo_weight_mode */
   int32_t plane_dtype;    /* tomo_dtype of the plane stack */
   int32_t angle_batch;    /* views per internal batch of tomo_reconstruct; 0 -> automatic */
+  int32_t fourier;        /* 1: also build the sampling matrix and workspace of
+                             tomo_fourier_reconstruct (needs n_vox in the FFT sizes below) */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
                                  when plan tables + workspace would exceed it */
 } tomo_params;
@@ -109,7 +111,8 @@ typedef struct {
  *   dist   host double [n], R_n (finite)
  *   stream hipStream_t the plan's set-up work runs on (synchronised before return)
  *   out    receives the plan; untouched on error.
- * Supported: M in {16, 32, 48, 64, 80, 96, 128}; N in [2, 1024]; K in [1, 2N]. */
+ * Supported: M in {16, 32, 48, 64, 80, 96, 128, 256}; N in [2, 1024]; K in [1, 2N];
+ * with fourier = 1 also N in {16, 32, 48, 64, 80, 96, 128, 256}. */
 tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* vaxes,
                       const double* dist, void* stream, tomo_plan_t* out);
 
@@ -146,13 +149,38 @@ tomo_status tomo_sync(tomo_plan_t plan, void* stream);
 tomo_status tomo_filtered_spectra(tomo_plan_t plan, const float* d_images, int32_t first,
                                   int32_t nb, float* d_out, void* stream);
 
+/* Fourier-space form of the method (the paper's own gridding): every view's
+ * spectrum DFT2(ln(I_n/I_in)), with its phase origin moved to the detector centre,
+ * is multiplied by the bracket H_n of eq. (11) (variant TOMO_EQ11) or left as is
+ * (TOMO_EQ12), and spread, with its complex conjugate at the reflected point, over
+ * the eight vertices of the N^3 grid of 3D frequencies (spacing 1/(N dx)) around
+ * its paraboloid point q_x u_n + q_y v_n - ewald (lambda q^2/2) d_n, half of the
+ * trilinear weights each (text after eq. 11).  The grid is divided by the
+ * regularised sampling matrix, S/(S^2 + eps_sampling); coefficients whose
+ * magnitude (in the images' DFT units) is below nsr * M / sqrt(S) are zeroed
+ * (Section 3; nsr = 0 keeps all); TOMO_EQ12 then multiplies by the bracket of
+ * eq. (12) at the common R and the 3D frequency |k|/(N dx); the inverse 3D Fourier
+ * integral at the voxel centres, times C = lambda / (4 pi sqrt(1 + sigma^2)), is
+ * written to d_volume (device float32 [N][N][N], overwritten).
+ * The gridding adds 64-bit fixed-point integers (unit from a bound on the sums),
+ * so results are bitwise reproducible.  Needs a plan made with fourier = 1;
+ * TOMO_EQ12 needs every dist[n] equal (else TOMO_EINVAL).  weight_mode, n_planes
+ * and plane_dtype do not enter.  d_images: device float32 [n][M][M].
+ * Synchronises the stream at the end to report TOMO_EDOMAIN. */
+typedef enum { TOMO_EQ11 = 11, TOMO_EQ12 = 12 } tomo_fourier_variant;
+tomo_status tomo_fourier_reconstruct(tomo_plan_t plan, const float* d_images, int32_t variant,
+                                     double nsr, float* d_volume, void* stream);
+
 /* Per-kernel timing (tracing).  While enabled, every kernel launch of the plan is
  * bracketed by two HIP events recorded on the launch's stream.  Kinds:
  *   0 = contrast + DFT + filter (spectra), 1 = depth planes (inverse FFTs),
- *   2 = gridding.  tomo_timing_read synchronises on the recorded events, adds
- * their elapsed times to the totals, and returns, per kind, total milliseconds
- * and launch counts since the last reset (reset != 0 clears them afterwards).
- * total_ms and launches are host arrays of 3 entries. */
+ *   2 = gridding, 3 = Fourier-space splat (bound, clear, splat),
+ *   4 = Fourier-space normalisation and inverse 3D FFT.
+ * tomo_timing_read synchronises on the recorded events, adds their elapsed
+ * times to the totals, and returns, per kind, total milliseconds and launch
+ * counts since the last reset (reset != 0 clears them afterwards).  total_ms and
+ * launches are host arrays of TOMO_TIMING_KINDS entries. */
+#define TOMO_TIMING_KINDS 5
 tomo_status tomo_timing_enable(tomo_plan_t plan, int32_t enable);
 tomo_status tomo_timing_read(tomo_plan_t plan, double* total_ms, int64_t* launches, int32_t reset);
 

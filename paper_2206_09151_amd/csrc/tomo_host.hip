@@ -33,6 +33,18 @@ struct tomo_plan_s {
   void* d_stack = nullptr;      // [batch][M][K][M] of the plane storage type
   float* d_scale = nullptr;     // [n] FP16 plane scale per view (powers of two)
   int* d_status = nullptr;
+  // Fourier-space form (params.fourier = 1)
+  int P = 0;                            // accumulator edge: N + 1 for even N, N for odd N
+  float4* d_ffilt = nullptr;            // [n][M][M] filter of the Fourier-space variant built last
+  int ffilt_variant = 0;                // 11, 12, or 0 before the first call
+  float* d_fview = nullptr;             // [n] per-view spectral bound (power-of-two scale)
+  double* d_ffix = nullptr;             // [2] fixed-point unit and its inverse
+  unsigned long long* d_facc = nullptr; // [P][P][P][2] fixed-point accumulator
+  unsigned long long* d_fsmat = nullptr;// [N][N][N] sampling matrix, 2^-32 units
+  float2* d_fgrid = nullptr;            // [N][N][N] complex grid of the inverse FFT
+  float2* d_tw3 = nullptr;              // [N] exp(+i 2 pi k / N)
+  bool same_R = true;
+  double R0 = 0.0;
   std::string err;
   // tracing: events around launches while timing is on
   struct Rec {
@@ -42,8 +54,8 @@ struct tomo_plan_s {
   bool timing = false;
   std::vector<hipEvent_t> pool;
   std::vector<Rec> recs;
-  double tot_ms[3] = {0, 0, 0};
-  long long launches[3] = {0, 0, 0};
+  double tot_ms[TOMO_TIMING_KINDS] = {};
+  long long launches[TOMO_TIMING_KINDS] = {};
 };
 
 namespace {
@@ -53,7 +65,7 @@ thread_local std::string g_plan_error;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 struct Resolved {
-  int N, M, K, n, npairs, batch;
+  int N, M, K, n, npairs, batch, P;
   size_t table_bytes, work_bytes;
 };
 
@@ -76,6 +88,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->weight_mode < 0 || p->weight_mode > 2) return "weight_mode must be 0, 1 or 2";
   if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
   if (p->angle_batch < 0) return "angle_batch must be >= 0";
+  if (p->fourier != 0 && p->fourier != 1) return "fourier must be 0 or 1";
   r->N = p->n_vox;
   r->M = p->n_pix ? p->n_pix : p->n_vox;
   if (p->n_pix < 0) return "n_pix must be >= 0";
@@ -100,6 +113,12 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   r->table_bytes = size_t(r->n) * sizeof(ViewGeom) + size_t(r->n) * qv + size_t(r->npairs) * r->M * 8 +
                    2 * size_t(r->M) * 8 + size_t(r->n) * 4 + 256;
   r->work_bytes = size_t(r->n) * qv + size_t(r->batch) * sv;
+  r->P = r->N + (r->N % 2 == 0 ? 1 : 0);
+  if (p->fourier) {
+    const size_t n3 = size_t(r->N) * r->N * r->N, p3 = size_t(r->P) * r->P * r->P;
+    r->table_bytes += size_t(r->n) * qv + n3 * 8 + size_t(r->N) * 8 + size_t(r->n) * 4 + 16;
+    r->work_bytes += p3 * 16 + n3 * 8;
+  }
   return "";
 }
 
@@ -107,6 +126,12 @@ std::string supported(const tomo_params* p, const Resolved& r) {
   if (!tomo::fft_supported(r.M)) {
     char b[160];
     std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128, 256)", r.M);
+    return b;
+  }
+  if (p->fourier && !tomo::fourier_grid_supported(r.N)) {
+    char b[160];
+    std::snprintf(b, sizeof b,
+                  "fourier = 1 needs n_vox in {16, 32, 48, 64, 80, 96, 128, 256} (got %d)", r.N);
     return b;
   }
   return "";
@@ -216,6 +241,13 @@ void free_plan(tomo_plan_s* pl) {
   (void)hipFree(pl->d_stack);
   (void)hipFree(pl->d_scale);
   (void)hipFree(pl->d_status);
+  (void)hipFree(pl->d_ffilt);
+  (void)hipFree(pl->d_fview);
+  (void)hipFree(pl->d_ffix);
+  (void)hipFree(pl->d_facc);
+  (void)hipFree(pl->d_fsmat);
+  (void)hipFree(pl->d_fgrid);
+  (void)hipFree(pl->d_tw3);
 }
 
 tomo_status fail(tomo_plan_s* pl, tomo_status st, const std::string& msg) {
@@ -311,6 +343,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   pl->n = r.n;
   pl->npairs = r.npairs;
   pl->batch = r.batch;
+  pl->P = r.P;
   pl->p.n_pix = r.M;
   pl->p.n_planes = r.K;
   if (pl->p.i_in == 0) pl->p.i_in = 1.0;
@@ -320,6 +353,8 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   std::vector<ViewGeom> geo;
   make_frames(dirs, vaxes, r.n, geo);
   for (int i = 0; i < r.n; ++i) geo[i].R = dist[i];
+  pl->R0 = dist[0];
+  for (int i = 1; i < r.n; ++i) pl->same_R = pl->same_R && dist[i] == dist[0];
   if (p->weight_mode == TOMO_RAMP_AXIS) axis_weights(dirs, r.n, geo);
   // Single-axis gather path: every v is exactly the y axis and u, d lie in the xz plane,
   // and detector rows line up with voxel rows (M - N even).
@@ -417,6 +452,23 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   }
   if ((e = tomo::launch_filter_table(fa, pl->d_geom, d_wtab, pl->d_filt, s)) != hipSuccess)
     return cleanup_fail(e, "filter-table kernel");
+  if (p->fourier) {
+    const size_t n3 = size_t(r.N) * r.N * r.N, p3 = size_t(r.P) * r.P * r.P;
+    std::vector<float2> tw3(r.N);
+    for (int k = 0; k < r.N; ++k) {
+      const double a = 2.0 * kPi * k / r.N;
+      tw3[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+    if ((e = dev_alloc(&pl->d_ffilt, mm * r.n)) != hipSuccess || (e = dev_alloc(&pl->d_fview, size_t(r.n))) ||
+        (e = dev_alloc(&pl->d_ffix, size_t(2))) || (e = dev_alloc(&pl->d_facc, 2 * p3)) ||
+        (e = dev_alloc(&pl->d_fsmat, n3)) || (e = dev_alloc(&pl->d_fgrid, n3)) ||
+        (e = dev_alloc(&pl->d_tw3, size_t(r.N))))
+      return cleanup_fail(e, "Fourier-space workspace allocation");
+    if ((e = hipMemcpyAsync(pl->d_tw3, tw3.data(), sizeof(float2) * r.N, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemsetAsync(pl->d_fsmat, 0, n3 * sizeof(unsigned long long), s)) ||
+        (e = tomo::launch_sampling_splat(fa, pl->d_geom, pl->d_fsmat, s)))
+      return cleanup_fail(e, "Fourier-space sampling matrix");
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup_fail(e, "plan synchronise");
   (void)hipFree(d_wtab);
   (void)hipFree(d_smat);
@@ -551,7 +603,7 @@ tomo_status tomo_timing_read(tomo_plan_t pl, double* total_ms, int64_t* launches
     pl->pool.push_back(r.b);
   }
   pl->recs.clear();
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < TOMO_TIMING_KINDS; ++k) {
     total_ms[k] = pl->tot_ms[k];
     launches[k] = pl->launches[k];
     if (reset) {
@@ -576,6 +628,65 @@ tomo_status tomo_filtered_spectra(tomo_plan_t pl, const float* d_images, int32_t
                                           reinterpret_cast<float2*>(d_out), pl->M, nb, s);
   if (e != hipSuccess) return dev_fail(pl, e, "spectra output kernel");
   return TOMO_OK;
+}
+
+tomo_status tomo_fourier_reconstruct(tomo_plan_t pl, const float* d_images, int32_t variant, double nsr,
+                                     float* d_volume, void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (!d_images || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
+  if (!pl->p.fourier) return fail(pl, TOMO_EINVAL, "plan was made with fourier = 0");
+  if (variant != TOMO_EQ11 && variant != TOMO_EQ12) return fail(pl, TOMO_EINVAL, "variant must be 11 or 12");
+  if (!(nsr >= 0) || !std::isfinite(nsr)) return fail(pl, TOMO_EINVAL, "nsr must be finite and >= 0");
+  if (variant == TOMO_EQ12 && !pl->same_R)
+    return fail(pl, TOMO_EINVAL, "eq. 12 needs one common distance R for every view");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tomo::FilterArgs fa{};
+  fa.n_views = pl->n;
+  fa.M = pl->M;
+  fa.N = pl->N;
+  fa.dx = pl->p.voxel_size;
+  fa.lambda = pl->p.wavelength;
+  fa.sigma = pl->p.sigma;
+  fa.epsilon = pl->p.epsilon;
+  fa.eps_sampling = pl->p.eps_sampling;
+  fa.ewald = pl->p.ewald;
+  fa.mode = pl->p.weight_mode;
+  hipError_t e = hipSuccess;
+  if (pl->ffilt_variant != variant) {
+    if ((e = tomo::launch_fourier_filter(fa, pl->d_geom, variant == TOMO_EQ12, pl->d_ffilt, s)) != hipSuccess)
+      return dev_fail(pl, e, "Fourier filter table");
+    pl->ffilt_variant = variant;
+  }
+  e = timed(pl, 0, s, [&] {
+    return tomo::launch_spectra(pl->M, d_images, pl->d_ffilt, pl->d_tw_fwd, pl->d_q, pl->d_status,
+                                1.0 / pl->p.i_in, pl->d_fview, pl->n, s, pl->d_tw2_fwd, pl->d_l1part);
+  });
+  if (e != hipSuccess) return dev_fail(pl, e, "spectra kernel");
+  e = timed(pl, 3, s, [&] {
+    return tomo::launch_fourier_splat(fa, pl->d_geom, pl->d_q, pl->d_fview, pl->d_ffix, pl->d_facc, pl->P, s);
+  });
+  if (e != hipSuccess) return dev_fail(pl, e, "Fourier splat kernels");
+  tomo::FourierNormArgs na{};
+  na.N = pl->N;
+  na.P = pl->P;
+  na.eq12 = variant == TOMO_EQ12;
+  na.ewald = pl->p.ewald;
+  na.eps_s = pl->p.eps_sampling;
+  na.nsr_m = nsr * pl->M;
+  const double cst = pl->p.wavelength / (4.0 * kPi * std::sqrt(1.0 + pl->p.sigma * pl->p.sigma));
+  const double nd = pl->N * pl->p.voxel_size;
+  na.out_scale = cst * pl->p.voxel_size * pl->p.voxel_size / (nd * nd * nd);
+  na.dx = pl->p.voxel_size;
+  na.lambda = pl->p.wavelength;
+  na.sigma = pl->p.sigma;
+  na.epsilon = pl->p.epsilon;
+  na.R = pl->R0;
+  e = timed(pl, 4, s, [&] {
+    return tomo::launch_fourier_inverse(na, pl->d_facc, pl->d_fsmat, pl->d_ffix, pl->d_fgrid, pl->d_tw3, d_volume, s);
+  });
+  if (e != hipSuccess) return dev_fail(pl, e, "Fourier normalise / inverse FFT kernels");
+  return tomo_sync(pl, stream);
 }
 
 }  // extern "C"

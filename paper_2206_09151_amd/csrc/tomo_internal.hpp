@@ -45,6 +45,29 @@ hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const
                                float4* filt, hipStream_t s);
 hipError_t launch_sampling(const FilterArgs& fa, const ViewGeom* geom, unsigned long long* smat,
                            double* wtab, hipStream_t s);
+hipError_t launch_sampling_splat(const FilterArgs& fa, const ViewGeom* geom, unsigned long long* smat,
+                                 hipStream_t s);
 hipError_t launch_spectra_out(const float4* q, float2* out, int M, int nb, hipStream_t s);
+
+// ---- Fourier-space form (eq. 11 / eq. 12 by 3D gridding)
+struct FourierNormArgs {
+  int N, P;            // grid edge; accumulator edge (N + 1 for even N)
+  int eq12, ewald;
+  double eps_s;        // regulariser of S^-1
+  double nsr_m;        // NSR * M (0: no threshold)
+  double out_scale;    // C dx^2 / (N dx)^3
+  double dx, lambda, sigma, epsilon, R;   // eq. 12 bracket
+};
+bool fourier_grid_supported(int N);
+// filt [n][M][M]: (H_n s, 0) (eq. 11) or (s, 0) (eq. 12), s = centring phase of the DFT.
+hipError_t launch_fourier_filter(const FilterArgs& fa, const ViewGeom* geom, int eq12, float4* filt,
+                                 hipStream_t s);
+// Fixed-point unit from view_scale [n] into fix[2], clear acc [P^3][2], splat q [n][M][M] (.xy).
+hipError_t launch_fourier_splat(const FilterArgs& fa, const ViewGeom* geom, const float4* q, const float* view_scale,
+                                double* fix, unsigned long long* acc, int P, hipStream_t s);
+// Normalise into grid [N^3] (FFT order), inverse 3D FFT (tw: [N] exp(+i 2 pi k/N)), real part into vol.
+hipError_t launch_fourier_inverse(const FourierNormArgs& a, const unsigned long long* acc,
+                                  const unsigned long long* smat, const double* fix, float2* grid, const float2* tw,
+                                  float* vol, hipStream_t s);
 
 }  // namespace tomo

@@ -22,6 +22,7 @@
 #include <cstdint>
 
 #include "fft.hpp"
+#include "geom.hpp"
 #include "tomo_internal.hpp"
 
 namespace tomo {
@@ -823,10 +824,6 @@ __global__ __launch_bounds__(256) void k_grid_gen(const InT* __restrict__ stack,
 }
 
 // ------------------------------------------------------------------ plan tables (FP64)
-__device__ __forceinline__ double signed_q(int k, int M, double dx) {
-  const int ks = (k < (M + 1) / 2) ? k : k - M;  // fftfreq order
-  return double(ks) / (double(M) * dx);
-}
 
 __device__ __forceinline__ double2 filter_value(const FilterArgs& fa, const ViewGeom& g,
                                                 const double* wv, int ky, int kx, int n) {
@@ -870,17 +867,6 @@ __global__ void k_filter_table(FilterArgs fa, const ViewGeom* __restrict__ geom,
 }
 
 // Sampling matrix in 2^-32 fixed point (integer atomics: order independent).
-constexpr double kFix = 4294967296.0;
-
-__device__ __forceinline__ void sample_point(const FilterArgs& fa, const ViewGeom& g, int ky, int kx,
-                                             double* p) {
-  const double qx = signed_q(kx, fa.M, fa.dx), qy = signed_q(ky, fa.M, fa.dx);
-  const double qz = -double(fa.ewald) * fa.lambda * (qx * qx + qy * qy) * 0.5;
-  const double sc = double(fa.N) * fa.dx;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) p[a] = (qx * g.u[a] + qy * g.v[a] + qz * g.d[a]) * sc;
-}
-
 __global__ void k_sampling_splat(FilterArgs fa, const ViewGeom* __restrict__ geom,
                                  unsigned long long* __restrict__ smat) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1084,6 +1070,13 @@ hipError_t launch_sampling(const FilterArgs& fa, const ViewGeom* geom, unsigned 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sampling_weights, grid, dim3(256), 0, s, fa, geom, smat, wtab);
+  return hipGetLastError();
+}
+
+hipError_t launch_sampling_splat(const FilterArgs& fa, const ViewGeom* geom, unsigned long long* smat,
+                                 hipStream_t s) {
+  const size_t total = size_t(fa.M) * fa.M * fa.n_views;
+  hipLaunchKernelGGL(k_sampling_splat, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, fa, geom, smat);
   return hipGetLastError();
 }
 

@@ -28,9 +28,10 @@ EXPORTED = [
     "tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_sync",
     "tomo_filtered_spectra", "tomo_workspace_bytes", "tomo_batch_capacity", "tomo_stack_bytes",
     "tomo_status_string", "tomo_last_error", "tomo_plan_error", "tomo_destroy",
-    "tomo_timing_enable", "tomo_timing_read",
+    "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct",
 ]
-KERNEL_KINDS = ("spectra", "planes", "grid")
+KERNEL_KINDS = ("spectra", "planes", "grid", "fsplat", "finverse")
+EQ11, EQ12 = 11, 12
 
 
 class TomoParams(ctypes.Structure):
@@ -40,7 +41,8 @@ class TomoParams(ctypes.Structure):
         ("voxel_size", ctypes.c_double), ("wavelength", ctypes.c_double), ("sigma", ctypes.c_double),
         ("epsilon", ctypes.c_double), ("eps_sampling", ctypes.c_double), ("i_in", ctypes.c_double),
         ("ewald", ctypes.c_int32), ("weight_mode", ctypes.c_int32), ("plane_dtype", ctypes.c_int32),
-        ("angle_batch", ctypes.c_int32), ("max_workspace_bytes", ctypes.c_size_t),
+        ("angle_batch", ctypes.c_int32), ("fourier", ctypes.c_int32),
+        ("max_workspace_bytes", ctypes.c_size_t),
     ]
 
 
@@ -76,9 +78,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_destroy.argtypes = [vp]
     lib.tomo_timing_enable.argtypes = [vp, i32]
     lib.tomo_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
+    lib.tomo_fourier_reconstruct.argtypes = [vp, vp, i32, ctypes.c_double, vp, vp]
     for name in ("tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_sync",
                  "tomo_filtered_spectra", "tomo_destroy", "tomo_batch_capacity", "tomo_timing_enable",
-                 "tomo_timing_read"):
+                 "tomo_timing_read", "tomo_fourier_reconstruct"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -107,13 +110,15 @@ class Params:
     i_in: float = 1.0
     plane_dtype: int = F32
     angle_batch: int = 0
+    fourier: int = 0
     max_workspace_bytes: int = 0
 
     def to_c(self) -> TomoParams:
         mode = _MODES[self.weight_mode] if isinstance(self.weight_mode, str) else int(self.weight_mode)
         return TomoParams(self.n_vox, self.n_pix, self.n_planes, self.n_angles, self.voxel_size,
                           self.wavelength, self.sigma, self.epsilon, self.eps_sampling, self.i_in,
-                          self.ewald, mode, self.plane_dtype, self.angle_batch, self.max_workspace_bytes)
+                          self.ewald, mode, self.plane_dtype, self.angle_batch, self.fourier,
+                          self.max_workspace_bytes)
 
 
 def _stream_ptr(stream) -> int | None:
@@ -197,13 +202,18 @@ class Plan:
         self._check(_LIB.tomo_filtered_spectra(self._h, _dptr(images), first, nb, _dptr(out),
                                                ctypes.c_void_p(_stream_ptr(stream))))
 
+    def fourier_reconstruct(self, images, volume, variant: int = EQ11, nsr: float = 0.0, stream=None):
+        """The Fourier-space form (eq. 11 or eq. 12 by 3D gridding, NSR filter)."""
+        self._check(_LIB.tomo_fourier_reconstruct(self._h, _dptr(images), int(variant), float(nsr), _dptr(volume),
+                                                  ctypes.c_void_p(_stream_ptr(stream))))
+
     def timing(self, enable: bool):
         self._check(_LIB.tomo_timing_enable(self._h, 1 if enable else 0))
 
     def timing_read(self, reset: bool = True) -> dict:
         """Per-kernel totals since the last reset: {kind: (total_ms, launches)}."""
-        ms = (ctypes.c_double * 3)()
-        cnt = (ctypes.c_int64 * 3)()
+        ms = (ctypes.c_double * len(KERNEL_KINDS))()
+        cnt = (ctypes.c_int64 * len(KERNEL_KINDS))()
         self._check(_LIB.tomo_timing_read(self._h, ms, cnt, 1 if reset else 0))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 

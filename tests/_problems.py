@@ -137,6 +137,14 @@ def make(name: str) -> Problem:
         lam, sig = 0.05e-10, 0.2
         imgs = _born(21, N, M, dx, lam, dirs, dist, sig, count=30)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+    if name == "n256":
+        # 256^3 Fourier grid (largest inverse-FFT size), few views
+        n, N, M, K = 4, 256, 256, 8
+        dirs = scan.uniform_sphere(22, n)
+        dist = np.full(n, 80e-10)
+        lam, sig = 0.05e-10, -0.1
+        imgs = _born(22, N, M, dx, lam, dirs, dist, sig, count=30)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
     raise KeyError(name)
 
 

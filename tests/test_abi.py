@@ -113,3 +113,21 @@ def test_null_plan_calls_are_rejected():
     assert lib.tomo_backpropagate(None, None, 0, 1, None, None) == tomo.EINVAL
     assert lib.tomo_destroy(None) == tomo.OK
     assert lib.tomo_batch_capacity(None) == 0
+
+
+def test_fourier_params_checked():
+    st, err = _plan_status(_params(fourier=2))
+    assert st == tomo.EINVAL and "fourier" in err
+    st, err = _plan_status(_params(n_vox=44, n_pix=48, fourier=1))
+    assert st == tomo.EUNSUPPORTED and "n_vox" in err
+    assert tomo.workspace_bytes(_params(fourier=1)) > tomo.workspace_bytes(_params())
+
+
+def test_timing_kinds_match_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+TOMO_TIMING_KINDS\s+(\d+)", text)
+    assert m and int(m.group(1)) == len(tomo.KERNEL_KINDS)
+
+
+def test_null_plan_fourier_call_is_rejected():
+    assert tomo.lib().tomo_fourier_reconstruct(None, None, 11, 0.0, None, None) == tomo.EINVAL

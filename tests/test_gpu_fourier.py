@@ -1,0 +1,129 @@
+"""GPU parity of the Fourier-space form (eq. 11 / eq. 12 by 3D gridding, NSR
+filter) against the FP64 oracle, through the C ABI.
+
+Bar: rel-L2 over all voxels <= 1e-5 (FP32 spectra and inverse FFT, 64-bit
+fixed-point gridding sums, FP64 normalisation).  With an NSR threshold both
+sides must make the same keep/zero decisions; the test picks the threshold in a
+gap of the oracle's coefficient ratios |A| sqrt(S) / M so that no coefficient
+sits within 1e-3 (relative) of it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import _problems
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+tomo = pytest.importorskip("paper_2206_09151_amd.tomo")
+
+FOURIER = ["axis32", "sampling32", "oddk16", "m80", "m96", "vaxes32", "pct64", "m256", "n256"]
+TOL = 1e-5
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _run(prob, variant=11, nsr=0.0, plan=None):
+    dev = torch.device("cuda:0")
+    if plan is None:
+        plan = tomo.Plan(prob.params(fourier=1), prob.dirs, prob.dist, vaxes=prob.vaxes)
+    imgs = torch.from_numpy(prob.images).to(dev)
+    vol = torch.full((prob.n_vox,) * 3, float("nan"), dtype=torch.float32, device=dev)
+    plan.fourier_reconstruct(imgs, vol, variant=variant, nsr=nsr)
+    torch.cuda.synchronize()
+    return vol.cpu().numpy().astype(np.float64), plan
+
+
+def _oracle(prob, variant=11, nsr=0.0):
+    return oracle.fourier_reconstruct(prob.images.astype(np.float64), prob.dirs, prob.dist,
+                                      prob.oracle_geometry(), vaxes=prob.vaxes, nsr=nsr, variant=variant)
+
+
+@pytest.mark.parametrize("name", FOURIER)
+def test_fourier_eq11_matches_oracle(name):
+    prob = _problems.make(name)
+    print(f"fourier eq11 {name}: N={prob.n_vox} M={prob.n_pix} n={prob.n}", flush=True)
+    got, _ = _run(prob)
+    want = _oracle(prob)
+    assert np.all(np.isfinite(got))
+    err = _rel(got, want)
+    print(f"  rel-L2 {err:.3g}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("name", ["axis32", "oddk16", "pct64", "m256"])
+def test_fourier_eq12_matches_oracle(name):
+    prob = _problems.make(name)
+    print(f"fourier eq12 {name}", flush=True)
+    got, _ = _run(prob, variant=12)
+    err = _rel(got, _oracle(prob, variant=12))
+    print(f"  rel-L2 {err:.3g}", flush=True)
+    assert err <= TOL
+
+
+def _nsr_in_gap(prob):
+    geo = prob.oracle_geometry()
+    u, v, d = oracle.frames(prob.dirs, prob.vaxes)
+    vals = oracle.fourier_values(oracle.centred_spectra(prob.images.astype(np.float64), geo), prob.dist, geo)
+    F, S = oracle.fourier_grid(vals, u, v, d, geo)
+    A = oracle.fourier_normalise(F, S, geo)
+    pos = S > 0
+    ratio = np.sort(np.abs(A[pos]) * np.sqrt(S[pos]) / geo.n_pix)
+    ratio = ratio[ratio > 0]
+    lo, hi = len(ratio) // 2, 9 * len(ratio) // 10
+    gaps = (ratio[lo + 1:hi + 1] - ratio[lo:hi]) / ratio[lo + 1:hi + 1]
+    i = lo + int(np.argmax(gaps))
+    assert gaps.max() > 2e-3
+    return float(np.sqrt(ratio[i] * ratio[i + 1]))
+
+
+@pytest.mark.parametrize("name", ["axis32", "vaxes32"])
+def test_fourier_nsr_threshold_matches_oracle(name):
+    prob = _problems.make(name)
+    nsr = _nsr_in_gap(prob)
+    print(f"fourier nsr {name}: nsr={nsr:.6g}", flush=True)
+    got, _ = _run(prob, nsr=nsr)
+    want = _oracle(prob, nsr=nsr)
+    full = _oracle(prob)
+    assert _rel(want, full) > 1e-3          # the threshold removes something
+    err = _rel(got, want)
+    print(f"  rel-L2 {err:.3g}", flush=True)
+    assert err <= TOL
+
+
+def test_fourier_is_bitwise_reproducible_and_variants_switch():
+    prob = _problems.make("sampling32")
+    a, plan = _run(prob)
+    b12, _ = _run(prob, variant=12, plan=plan)
+    b, _ = _run(prob, plan=plan)
+    assert np.array_equal(a, b)
+    assert _rel(b12, _oracle(prob, variant=12)) <= TOL
+    plan.destroy()
+
+
+def test_fourier_errors():
+    prob = _problems.make("axis32")
+    dev = torch.device("cuda:0")
+    imgs = torch.from_numpy(prob.images).to(dev)
+    vol = torch.empty((prob.n_vox,) * 3, dtype=torch.float32, device=dev)
+    plain = tomo.Plan(prob.params(), prob.dirs, prob.dist)
+    with pytest.raises(tomo.TomoError) as ei:
+        plain.fourier_reconstruct(imgs, vol)
+    assert ei.value.status == tomo.EINVAL
+    dist = np.linspace(40e-10, 60e-10, prob.n)
+    plan = tomo.Plan(prob.params(fourier=1), prob.dirs, dist)
+    with pytest.raises(tomo.TomoError) as ei:
+        plan.fourier_reconstruct(imgs, vol, variant=12)
+    assert ei.value.status == tomo.EINVAL
+    with pytest.raises(tomo.TomoError):
+        plan.fourier_reconstruct(imgs, vol, variant=13)
+    bad = imgs.clone()
+    bad[1, 3, 4] = -1.0
+    with pytest.raises(tomo.TomoError) as ei:
+        plan.fourier_reconstruct(bad, vol)
+    assert ei.value.status == tomo.EDOMAIN
+    plain.destroy()
+    plan.destroy()
