@@ -70,7 +70,7 @@ def copy_probe(mib: int):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fft.hpp", "tomo_kernels.hip"):
+    for f in ("fft.hpp", "geom.hpp", "tomo_kernels.hip", "fourier_kernels.hip"):
         with open(os.path.join(ROOT, "paper_2206_09151_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
