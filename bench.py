@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dt_ewald_128")
+    ap.add_argument("--workload", default="dt_ewald_128",
+                    help="dt_ewald_128 | ct_pct_64 | xray_jitter_256 | batch64 (64 uneven jobs in one graph)")
     ap.add_argument("--angle-batch", type=int, default=0)
     ap.add_argument("--plane-dtype", default="f32", choices=["f32", "bf16", "fp16"],
                     help="storage type of the plane stacks (interpolation and sums stay FP32)")
@@ -48,6 +49,8 @@ def parse():
     ap.add_argument("--method", default="realspace", choices=["realspace", "fourier"])
     ap.add_argument("--variant", type=int, default=11, choices=[11, 12], help="Fourier-space form: eq. 11 or 12")
     ap.add_argument("--nsr", type=float, default=0.0, help="Fourier-space noise filter level (0: off)")
+    ap.add_argument("--fourier-mode", type=int, default=1, choices=[1, 2],
+                    help="Fourier-space gridding: 1 plan-time operator (gather), 2 per-call atomic splat")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -76,15 +79,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool, sbytes: int = 4) -> float:
-    """Compulsory HBM bytes of one launch over nb views; sbytes = bytes per stored
-    plane value."""
+def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool, sbytes: int = 4, fourier_mode: int = 1,
+                      entries: int = 0) -> float:
+    """Compulsory HBM bytes of the launches of one kind in one step over nb views;
+    sbytes = bytes per stored plane value; entries = non-zeros of the Fourier-space
+    gridding operator."""
     N, M, K = w.n_vox, w.M, w.K
     P = N + (1 - N % 2)
-    if kind == "fsplat":    # filtered spectra read + accumulator written once (clear) and updated once
-        return nb * 16.0 * M * M + 2 * 16.0 * P ** 3
-    if kind == "finverse":  # accumulator + S read, complex grid written, 3 FFT passes, volume written
-        return 16.0 * P ** 3 + 8.0 * N ** 3 + 8.0 * N ** 3 + 2 * 2 * 8.0 * N ** 3 + 8.0 * N ** 3 + 4.0 * N ** 3
+    fft3 = 2 * (8.0 + 8.0) * N ** 3 + (8.0 + 4.0) * N ** 3     # three passes, the last writes the real part
+    if kind == "fgrid":
+        if fourier_mode == 1:   # operator entries + row offsets + spectra + S read, complex grid written
+            return 8.0 * entries + 4.0 * P ** 3 + nb * 16.0 * M * M + 8.0 * N ** 3 + 8.0 * N ** 3
+        return nb * 16.0 * M * M + 2 * 16.0 * P ** 3           # spectra read, accumulator cleared and updated
+    if kind == "finverse":
+        if fourier_mode == 1:
+            return fft3
+        return 16.0 * P ** 3 + 8.0 * N ** 3 + 8.0 * N ** 3 + fft3   # + normalisation pass
     if kind == "spectra":   # image read + filter table read + Q write (16 B per coefficient each)
         return nb * (4.0 * M * M + 16.0 * M * M + 16.0 * M * M)
     if kind == "planes":    # Q read once per view + plane stack write
@@ -116,6 +126,9 @@ def main():
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
               "multi-GPU runs are not part of it", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        run_batch(args)
+        return
     import torch
     from synth import workloads
     from paper_2206_09151_amd import tomo
@@ -132,7 +145,7 @@ def main():
     params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
                          sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in,
-                         angle_batch=args.angle_batch, fourier=1 if args.method == "fourier" else 0,
+                         angle_batch=args.angle_batch, fourier=args.fourier_mode if args.method == "fourier" else 0,
                          plane_dtype={"f32": tomo.F32, "bf16": tomo.BF16, "fp16": tomo.F16}[args.plane_dtype])
     stream = torch.cuda.current_stream()
     plan = tomo.Plan(params, dirs, dist, stream=stream)
@@ -178,8 +191,9 @@ def main():
                 continue
             # bytes of all launches of one step (the first batch writes V without reading it)
             sb = 4 if args.plane_dtype == "f32" else 2
-            if kind == "spectra" or fourier:   # one launch over all views per step
-                step_bytes = algorithmic_bytes(kind, w, w.n_views, True, sb)
+            if kind == "spectra" or fourier:   # launches over all views per step
+                step_bytes = algorithmic_bytes(kind, w, w.n_views, True, sb, args.fourier_mode,
+                                               plan.fourier_entries)
                 per_launch = step_bytes / cnt * args.steps
             else:
                 step_bytes = sum(algorithmic_bytes(kind, w, min(batch, w.n_views - b * batch), b == 0, sb)
@@ -255,7 +269,8 @@ def main():
 
     out = {
         "metric": "voxel*angle updates/s (DT backprop+gridding)",
-        "method": args.method if not fourier else f"fourier_eq{args.variant}",
+        "method": args.method if not fourier else
+        f"fourier_eq{args.variant}_{'operator' if args.fourier_mode == 1 else 'splat'}",
         "value": value,
         "unit": "voxel*angle updates/s",
         "n_gpus": 1,
@@ -270,13 +285,143 @@ def main():
         "config": {"workload": w.name, "n_vox": w.n_vox, "n_pix": w.M, "n_planes": w.K,
                    "plane_storage": args.plane_dtype,
                    "n_views": w.n_views, "ewald": w.ewald, "weight_mode": w.weight_mode,
-                   "angle_batch": batch, "updates_per_step": updates},
+                   "angle_batch": batch, "updates_per_step": updates,
+                   **({"fourier_mode": args.fourier_mode, "operator_entries": plan.fourier_entries,
+                       "variant": args.variant, "nsr": args.nsr} if fourier else {})},
         "rel_l2_vs_fp64": rel_l2,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _make_job(w):
+    from synth import workloads
+    ph, dirs, dist, imgs = workloads.make_workload(w)
+    return dirs, dist, imgs.astype(np.float32)
+
+
+def run_batch(args):
+    """64 uneven jobs (N in {64..192}, 60-240 views, single-axis and sphere scans) as one
+    recorded graph: a step is one launch of all jobs; value = total N^3 n of the jobs
+    per second.  Per-kernel figures come from one eager pass over the jobs with the
+    library's event timing."""
+    import multiprocessing as mp
+    from synth import workloads
+    jobs = workloads.batch_jobs()
+    t0 = time.time()
+    # inputs are drawn before anything touches the GPU (worker processes are plain CPU work)
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        data = pool.map(_make_job, jobs)
+    print(f"[bench] batch64: {len(jobs)} jobs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    import torch
+    from paper_2206_09151_amd import tomo
+    dev = torch.device("cuda:0")
+    plans, imgs, vols = [], [], []
+    for w, (dirs, dist, im) in zip(jobs, data):
+        params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
+                             sigma=w.sigma, epsilon=w.epsilon, ewald=w.ewald, weight_mode=w.weight_mode,
+                             eps_sampling=w.eps_sampling, i_in=w.i_in)
+        plans.append(tomo.Plan(params, dirs, dist))
+        imgs.append(torch.from_numpy(im).to(dev))
+        vols.append(torch.empty((w.n_vox,) * 3, dtype=torch.float32, device=dev))
+    batch = tomo.Batch(plans, imgs, vols)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        batch.launch(stream)
+    batch.sync(stream)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        batch.launch(stream)
+    batch.sync(stream)
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    updates = float(sum(w.updates for w in jobs))
+    value = updates / (ms * 1e-3)
+    print(f"[bench] batch64: {ms:.3f} ms/step, {value:.4g} updates/s", file=sys.stderr, flush=True)
+
+    kernels = roofline = None
+    if not args.no_kernel_timing:
+        tot = {}
+        for pl, w, im, v in zip(plans, jobs, imgs, vols):
+            pl.timing(True)
+            pl.timing_read(reset=True)
+            pl.reconstruct(im, v, stream=stream)
+            pl.timing(False)
+            nb_all = -(-w.n_views // pl.batch)
+            for kind, (ms_k, cnt) in pl.timing_read(reset=True).items():
+                if cnt == 0:
+                    continue
+                if kind == "spectra":
+                    b = algorithmic_bytes(kind, w, w.n_views, True)
+                else:
+                    b = sum(algorithmic_bytes(kind, w, min(pl.batch, w.n_views - i * pl.batch), i == 0)
+                            for i in range(nb_all))
+                a = tot.setdefault(kind, [0.0, 0, 0.0])
+                a[0] += ms_k
+                a[1] += cnt
+                a[2] += b
+        kernels = {k: {"ms_total_eager": v[0], "launches": v[1], "algorithmic_bytes": v[2],
+                       "GBps": v[2] / (v[0] * 1e-3) / 1e9} for k, v in tot.items()}
+        dom = max(kernels, key=lambda kk: kernels[kk]["ms_total_eager"])
+        achieved = kernels[dom]["GBps"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "note": "eager pass over the 64 jobs with library event timing (the graph holds no events)",
+                    "kernel_source_hash": kernel_source_hash()}
+        print(f"[bench] kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
+
+    cpu = rel_l2 = None
+    if not args.no_cpu:
+        import oracle
+        j = min(range(len(jobs)), key=lambda k: jobs[k].updates)
+        w = jobs[j]
+        dirs, dist, im = data[j]
+        nv = min(args.cpu_views, w.n_views)
+        geo = oracle.Geometry(w.n_vox, w.M, w.K, w.voxel, w.wavelength, w.sigma, w.epsilon, ewald=w.ewald,
+                              weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in)
+        t = time.perf_counter()
+        ref = oracle.reconstruct_views(im.astype(np.float64), dirs, dist, geo, views=np.arange(nv))
+        cpu_s = time.perf_counter() - t
+        cpu = {"value": float(w.n_vox) ** 3 * nv / cpu_s, "unit": "voxel*angle updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"job {j} (N={w.n_vox}, {w.geometry}): {nv} of {w.n_views} views, full volume, "
+                         f"{cpu_s:.1f} s (numpy FP64, single thread)"}
+        pl = plans[j]
+        part = torch.zeros_like(vols[j])
+        st = torch.empty(pl.stack_shape(min(pl.batch, nv)), dtype=torch.float32, device=dev)
+        for first in range(0, nv, pl.batch):
+            nb = min(pl.batch, nv - first)
+            pl.backpropagate(imgs[j][first:first + nb].contiguous(), first, nb, st, stream=stream)
+            pl.grid(st, first, nb, part, stream=stream)
+        torch.cuda.synchronize()
+        got = part.cpu().numpy().astype(np.float64)
+        rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    out = {
+        "metric": "voxel*angle updates/s (DT backprop+gridding)",
+        "method": "realspace_batch_graph",
+        "value": value,
+        "unit": "voxel*angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch64", "jobs": len(jobs), "n_vox": sorted({w.n_vox for w in jobs}),
+                   "views_range": [min(w.n_views for w in jobs), max(w.n_views for w in jobs)],
+                   "updates_per_step": updates},
+        "rel_l2_vs_fp64": rel_l2,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    batch.destroy()
 
 
 if __name__ == "__main__":

@@ -96,8 +96,11 @@ typedef struct {
   int32_t weight_mode;    /* tomo_weight_mode */
   int32_t plane_dtype;    /* tomo_dtype of the plane stack */
   int32_t angle_batch;    /* views per internal batch of tomo_reconstruct; 0 -> automatic */
-  int32_t fourier;        /* 1: also build the sampling matrix and workspace of
-                             tomo_fourier_reconstruct (needs n_vox in the FFT sizes below) */
+  int32_t fourier;        /* workspace of tomo_fourier_reconstruct (needs n_vox in the FFT
+                             sizes below): 0 none; 1 the gridding operator, built here (8 bytes
+                             per non-zero trilinear weight, at most 64 n M^2 bytes), used as a
+                             gather per call; 2 a per-call splat with 64-bit integer atomics
+                             (16 (N+1)^3 bytes) */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
                                  when plan tables + workspace would exceed it */
 } tomo_params;
@@ -111,8 +114,8 @@ typedef struct {
  *   dist   host double [n], R_n (finite)
  *   stream hipStream_t the plan's set-up work runs on (synchronised before return)
  *   out    receives the plan; untouched on error.
- * Supported: M in {16, 32, 48, 64, 80, 96, 128, 256}; N in [2, 1024]; K in [1, 2N];
- * with fourier = 1 also N in {16, 32, 48, 64, 80, 96, 128, 256}. */
+ * Supported: M in {16, 32, 48, 64, 80, 96, 128, 160, 192, 256}; N in [2, 1024]; K in [1, 2N];
+ * with fourier = 1 or 2 also N in {16, 32, 48, 64, 80, 96, 128, 256}. */
 tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* vaxes,
                       const double* dist, void* stream, tomo_plan_t* out);
 
@@ -162,8 +165,10 @@ tomo_status tomo_filtered_spectra(tomo_plan_t plan, const float* d_images, int32
  * eq. (12) at the common R and the 3D frequency |k|/(N dx); the inverse 3D Fourier
  * integral at the voxel centres, times C = lambda / (4 pi sqrt(1 + sigma^2)), is
  * written to d_volume (device float32 [N][N][N], overwritten).
- * The gridding adds 64-bit fixed-point integers (unit from a bound on the sums),
- * so results are bitwise reproducible.  Needs a plan made with fourier = 1;
+ * With fourier = 1 every vertex sums its contributions in FP64 in ascending sample
+ * order (the plan sorted the operator's entries); with fourier = 2 the splat adds 64-bit
+ * fixed-point integers (unit from a bound on the sums).  Either way results are
+ * bitwise reproducible.  Needs a plan made with fourier = 1 or 2;
  * TOMO_EQ12 needs every dist[n] equal (else TOMO_EINVAL).  weight_mode, n_planes
  * and plane_dtype do not enter.  d_images: device float32 [n][M][M].
  * Synchronises the stream at the end to report TOMO_EDOMAIN. */
@@ -174,8 +179,9 @@ tomo_status tomo_fourier_reconstruct(tomo_plan_t plan, const float* d_images, in
 /* Per-kernel timing (tracing).  While enabled, every kernel launch of the plan is
  * bracketed by two HIP events recorded on the launch's stream.  Kinds:
  *   0 = contrast + DFT + filter (spectra), 1 = depth planes (inverse FFTs),
- *   2 = gridding, 3 = Fourier-space splat (bound, clear, splat),
- *   4 = Fourier-space normalisation and inverse 3D FFT.
+ *   2 = gridding, 3 = Fourier-space gridding (fourier = 1: operator gather with the
+ *   normalisation; fourier = 2: bound, clear, splat), 4 = Fourier-space normalisation
+ *   (fourier = 2 only) and inverse 3D FFT.
  * tomo_timing_read synchronises on the recorded events, adds their elapsed
  * times to the totals, and returns, per kind, total milliseconds and launch
  * counts since the last reset (reset != 0 clears them afterwards).  total_ms and
@@ -184,7 +190,35 @@ tomo_status tomo_fourier_reconstruct(tomo_plan_t plan, const float* d_images, in
 tomo_status tomo_timing_enable(tomo_plan_t plan, int32_t enable);
 tomo_status tomo_timing_read(tomo_plan_t plan, double* total_ms, int64_t* launches, int32_t reset);
 
-/* Bytes of plan tables + workspace that tomo_plan would allocate for p (0 if p is invalid). */
+/* Batched uneven jobs: many independent reconstructions (each with its own plan, of any
+ * size and geometry) recorded once into one HIP graph and launched with one call.
+ * tomo_batch_create records, for job j, every kernel tomo_reconstruct would launch for
+ * plans[j] on d_images[j] -> d_volumes[j] (no synchronisation inside); the jobs are dealt
+ * to `lanes` parallel branches of the graph (0 -> min(count, 8)), longest job first onto
+ * the least loaded branch (work = N^3 n), so kernels of different jobs run concurrently.
+ *   plans      host array of count distinct plans (each job needs its own workspace)
+ *   d_images   host array of count device pointers, float32 [n_j][M_j][M_j]
+ *   d_volumes  host array of count device pointers, float32 [N_j][N_j][N_j] (overwritten)
+ * The buffers and plans are bound into the graph: they must stay valid and at the same
+ * addresses for every launch, and the plans must not run other work concurrently with a
+ * launch.  Plan timing is off while recording (the graph holds no event nodes).
+ * tomo_batch_launch enqueues the graph on stream (asynchronous); tomo_batch_sync
+ * synchronises stream and reports TOMO_EDOMAIN if any job saw an invalid image value
+ * (tomo_batch_error names the first such job).  Errors of tomo_batch_create are reported
+ * by tomo_plan_error. */
+typedef struct tomo_batch_s* tomo_batch_t;
+tomo_status tomo_batch_create(const tomo_plan_t* plans, const float* const* d_images, float* const* d_volumes,
+                              int32_t count, int32_t lanes, tomo_batch_t* out);
+tomo_status tomo_batch_launch(tomo_batch_t batch, void* stream);
+tomo_status tomo_batch_sync(tomo_batch_t batch, void* stream);
+const char* tomo_batch_error(tomo_batch_t batch);
+tomo_status tomo_batch_destroy(tomo_batch_t batch);
+
+/* Non-zero entries of the plan's Fourier-space gridding operator (0 unless fourier = 1). */
+size_t tomo_fourier_entries(tomo_plan_t plan);
+
+/* Bytes of plan tables + workspace that tomo_plan would allocate for p (0 if p is invalid;
+ * with fourier = 1 an upper bound: the operator's exact size is known after planning). */
 size_t tomo_workspace_bytes(const tomo_params* p);
 
 /* Views per internal batch of tomo_reconstruct (plane stacks held at once). */

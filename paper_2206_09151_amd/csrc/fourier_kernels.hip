@@ -24,6 +24,13 @@
 //                centre origin); written in FFT order.
 //   k_fft_axis   inverse 1D FFTs of all lines along one axis of the N^3 grid, staged
 //                through LDS, in place; the last pass writes the real part, the volume.
+//
+// Precomputed gridding operator (plan time): the vertex -> (sample, weight) lists do not
+// depend on the images, so the plan stores them as a compressed sparse row matrix over
+// the P^3 vertices (k_fop_count, a host prefix sum, k_fop_fill, k_fop_sort: entries of a
+// vertex in ascending sample order).  Per call, k_fgather forms F(k) and F(-k) of every
+// grid vertex as FP64 sums in that fixed order -- deterministic, no atomics -- and applies
+// the k_fnorm steps in the same kernel.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -118,23 +125,14 @@ __global__ __launch_bounds__(256) void k_fsplat(FilterArgs fa, const ViewGeom* _
 }
 
 // ------------------------------------------------------------------ normalise
-__global__ __launch_bounds__(256) void k_fnorm(FourierNormArgs a, const unsigned long long* __restrict__ acc,
-                                               const unsigned long long* __restrict__ smat,
-                                               const double* __restrict__ fix, float2* __restrict__ grid) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int N = a.N, P = a.P;
-  const size_t n3 = size_t(N) * N * N;
-  if (i >= n3) return;
-  const int jx = int(i % N), jy = int((i / N) % N), jz = int(i / (size_t(N) * N));
+// Steps after the Hermitian fold for grid vertex i = (jz, jy, jx): S^-1, NSR threshold,
+// eq. 12 bracket, centring phase and constant; stores into the FFT-order grid.
+__device__ __forceinline__ void finish_vertex(const FourierNormArgs& a, size_t i, int jx, int jy, int jz, double re,
+                                              double im, const unsigned long long* __restrict__ smat,
+                                              float2* __restrict__ grid) {
+  const int N = a.N;
   const int lo = -(N / 2);
   const int kx = jx + lo, ky = jy + lo, kz = jz + lo;
-  // index of -k: -k - lo = -j - 2 lo, inside [0, P)
-  const int mx = -jx - 2 * lo, my = -jy - 2 * lo, mz = -jz - 2 * lo;
-  const ulonglong2 f = reinterpret_cast<const ulonglong2*>(acc)[(size_t(jz) * P + jy) * P + jx];
-  const ulonglong2 g = reinterpret_cast<const ulonglong2*>(acc)[(size_t(mz) * P + my) * P + mx];
-  const double inv_unit = fix[1];
-  double re = 0.5 * (double((long long)f.x) + double((long long)g.x)) * inv_unit;
-  double im = 0.5 * (double((long long)f.y) - double((long long)g.y)) * inv_unit;
   const double S = double(smat[i]) / kFix;
   const double ws = S / (S * S + a.eps_s);
   re *= ws;
@@ -164,6 +162,206 @@ __global__ __launch_bounds__(256) void k_fnorm(FourierNormArgs a, const unsigned
   const double oii = (im * pc - re * ps) * a.out_scale;
   const int fx = (kx + N) % N, fy = (ky + N) % N, fz = (kz + N) % N;
   grid[(size_t(fz) * N + fy) * N + fx] = make_float2(float(orr), float(oii));
+}
+
+__global__ __launch_bounds__(256) void k_fnorm(FourierNormArgs a, const unsigned long long* __restrict__ acc,
+                                               const unsigned long long* __restrict__ smat,
+                                               const double* __restrict__ fix, float2* __restrict__ grid) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int N = a.N, P = a.P;
+  const size_t n3 = size_t(N) * N * N;
+  if (i >= n3) return;
+  const int jx = int(i % N), jy = int((i / N) % N), jz = int(i / (size_t(N) * N));
+  const int lo = -(N / 2);
+  // index of -k: -k - lo = -j - 2 lo, inside [0, P)
+  const int mx = -jx - 2 * lo, my = -jy - 2 * lo, mz = -jz - 2 * lo;
+  const ulonglong2 f = reinterpret_cast<const ulonglong2*>(acc)[(size_t(jz) * P + jy) * P + jx];
+  const ulonglong2 g = reinterpret_cast<const ulonglong2*>(acc)[(size_t(mz) * P + my) * P + mx];
+  const double inv_unit = fix[1];
+  const double re = 0.5 * (double((long long)f.x) + double((long long)g.x)) * inv_unit;
+  const double im = 0.5 * (double((long long)f.y) - double((long long)g.y)) * inv_unit;
+  finish_vertex(a, i, jx, jy, jz, re, im, smat, grid);
+}
+
+// ------------------------------------------------------------------ gridding operator
+// Trilinear taps of sample i (view n, bin (ky, kx)) on the P^3 vertex grid with positive
+// weight: calls f(cell, w) in a fixed tap order.
+template <class F>
+__device__ __forceinline__ void for_each_tap(const FilterArgs& fa, const ViewGeom& g, int ky, int kx, int P, F&& f) {
+  double p[3];
+  sample_point(fa, g, ky, kx, p);
+  const int lo = -(fa.N / 2);
+  int i0[3];
+  double t[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double fl = floor(p[a] - lo);
+    i0[a] = int(fl);
+    t[a] = (p[a] - lo) - fl;
+  }
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const int jx = i0[0] + cx, jy = i0[1] + cy, jz = i0[2] + cz;
+        if (unsigned(jx) >= unsigned(P) || unsigned(jy) >= unsigned(P) || unsigned(jz) >= unsigned(P)) continue;
+        const double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+        if (w > 0.0) f((size_t(jz) * P + jy) * P + jx, w);
+      }
+}
+
+__global__ __launch_bounds__(256) void k_fop_count(FilterArgs fa, const ViewGeom* __restrict__ geom, int P,
+                                                   unsigned* __restrict__ count) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t per = size_t(fa.M) * fa.M;
+  if (i >= per * fa.n_views) return;
+  const int n = int(i / per);
+  const int ky = int((i % per) / fa.M), kx = int(i % fa.M);
+  for_each_tap(fa, geom[n], ky, kx, P, [&](size_t cell, double) { atomicAdd(count + cell, 1u); });
+}
+
+__global__ __launch_bounds__(256) void k_fop_fill(FilterArgs fa, const ViewGeom* __restrict__ geom, int P,
+                                                  const unsigned* __restrict__ row_ptr, unsigned* __restrict__ cursor,
+                                                  int2* __restrict__ ent) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t per = size_t(fa.M) * fa.M;
+  if (i >= per * fa.n_views) return;
+  const int n = int(i / per);
+  const int ky = int((i % per) / fa.M), kx = int(i % fa.M);
+  for_each_tap(fa, geom[n], ky, kx, P, [&](size_t cell, double w) {
+    const unsigned slot = atomicAdd(cursor + cell, 1u);
+    // the counting pass visited the same taps; the guard keeps every store in the vertex's range
+    if (row_ptr[cell] + slot < row_ptr[cell + 1])
+      ent[size_t(row_ptr[cell]) + slot] = make_int2(int(i), __float_as_int(float(w)));
+  });
+}
+
+// Entries of every vertex in ascending sample order (insertion sort; lists are short
+// except near the origin and the rotation axis).
+__global__ __launch_bounds__(256) void k_fop_sort(size_t cells, const unsigned* __restrict__ row_ptr,
+                                                  int2* __restrict__ ent) {
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  const unsigned b = row_ptr[c], e = row_ptr[c + 1];
+  for (unsigned j = b + 1; j < e; ++j) {
+    const int2 v = ent[j];
+    unsigned k = j;
+    while (k > b && ent[k - 1].x > v.x) {
+      ent[k] = ent[k - 1];
+      --k;
+    }
+    ent[k] = v;
+  }
+}
+
+// Sum of w * value over a vertex's entries (FP64, ascending sample order).  Four entries
+// are fetched per round so that four spectrum loads are in flight at once.
+__device__ __forceinline__ void gather_vertex(size_t cell, const unsigned* __restrict__ row_ptr,
+                                              const int2* __restrict__ ent, const float2* __restrict__ q2,
+                                              double& re, double& im) {
+  re = 0.0;
+  im = 0.0;
+  const unsigned b = row_ptr[cell], e = row_ptr[cell + 1];
+  unsigned j = b;
+  for (; j + 4 <= e; j += 4) {
+    int2 v[4];
+    float2 s[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = ent[j + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] = q2[2 * size_t(v[u].x)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double w = double(__int_as_float(v[u].y));
+      re += w * double(s[u].x);
+      im += w * double(s[u].y);
+    }
+  }
+  for (; j < e; ++j) {
+    const int2 v = ent[j];
+    const float2 s = q2[2 * size_t(v.x)];
+    const double w = double(__int_as_float(v.y));
+    re += w * double(s.x);
+    im += w * double(s.y);
+  }
+}
+
+// Lane-strided partial sum of a vertex's entries (the wave-cooperative path).
+__device__ __forceinline__ void gather_strided(unsigned b, unsigned e, int lane, const int2* __restrict__ ent,
+                                               const float2* __restrict__ q2, double& re, double& im) {
+  for (unsigned j = b + lane; j < e; j += 64) {
+    const int2 v = ent[j];
+    const float2 s = q2[2 * size_t(v.x)];
+    const double w = double(__int_as_float(v.y));
+    re += w * double(s.x);
+    im += w * double(s.y);
+  }
+}
+
+// Entries above which a vertex pair is summed by the whole wave (vertices near the
+// origin and the rotation axis collect one entry per view).
+constexpr unsigned kHeavy = 48;
+
+// One thread per pair (k, -k): the Hermitian fold gives A(-k) = conj A(k), so both
+// vertices are finished from the same two sums.  The thread of the pair's lower flat
+// index owns it; a vertex whose mirror lies outside the grid (the lowest plane of an
+// even N) owns itself.  Pairs with more than kHeavy entries are summed by all 64 lanes
+// of the wave (lane-strided partial sums, then a fixed butterfly), one pair after the
+// other; the rest sequentially by their owner.  Both orders are fixed: deterministic.
+__global__ __launch_bounds__(256) void k_fgather(FourierNormArgs a, const unsigned* __restrict__ row_ptr,
+                                                 const int2* __restrict__ ent, const float4* __restrict__ q,
+                                                 const unsigned long long* __restrict__ smat,
+                                                 float2* __restrict__ grid) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int N = a.N, P = a.P;
+  const size_t n3 = size_t(N) * N * N;
+  const int jx = int(i % N), jy = int((i / N) % N), jz = int(i / (size_t(N) * N));
+  const int lo = -(N / 2);
+  const int mx = -jx - 2 * lo, my = -jy - 2 * lo, mz = -jz - 2 * lo;
+  const bool mirror_in = mx < N && my < N && mz < N;
+  const size_t mi = (size_t(mz) * N + my) * N + mx;
+  const bool owner = i < n3 && !(mirror_in && mi < i);
+  const float2* q2 = reinterpret_cast<const float2*>(q);
+  unsigned bk = 0, ek = 0, bm = 0, em = 0;
+  if (owner) {
+    const size_t ck = (size_t(jz) * P + jy) * P + jx, cm = (size_t(mz) * P + my) * P + mx;
+    bk = row_ptr[ck];
+    ek = row_ptr[ck + 1];
+    bm = row_ptr[cm];
+    em = row_ptr[cm + 1];
+  }
+  const bool heavy = owner && (ek - bk) + (em - bm) > kHeavy;
+  double fr = 0.0, fi = 0.0, gr = 0.0, gi = 0.0;
+  if (owner && !heavy) {
+    gather_vertex((size_t(jz) * P + jy) * P + jx, row_ptr, ent, q2, fr, fi);
+    gather_vertex((size_t(mz) * P + my) * P + mx, row_ptr, ent, q2, gr, gi);
+  }
+  unsigned long long todo = __ballot(heavy);
+  while (todo) {
+    const int src = __ffsll(static_cast<long long>(todo)) - 1;
+    todo &= todo - 1;
+    const unsigned b1 = __shfl(bk, src, 64), e1 = __shfl(ek, src, 64);
+    const unsigned b2 = __shfl(bm, src, 64), e2 = __shfl(em, src, 64);
+    double pr = 0.0, pi = 0.0, sr = 0.0, si = 0.0;
+    gather_strided(b1, e1, lane, ent, q2, pr, pi);
+    gather_strided(b2, e2, lane, ent, q2, sr, si);
+    for (int off = 32; off > 0; off >>= 1) {
+      pr += __shfl_xor(pr, off, 64);
+      pi += __shfl_xor(pi, off, 64);
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
+    if (lane == src) {
+      fr = pr;
+      fi = pi;
+      gr = sr;
+      gi = si;
+    }
+  }
+  if (!owner) return;
+  const double ar = 0.5 * (fr + gr), ai = 0.5 * (fi - gi);
+  finish_vertex(a, i, jx, jy, jz, ar, ai, smat, grid);
+  if (mirror_in && mi != i) finish_vertex(a, mi, mx, my, mz, ar, -ai, smat, grid);
 }
 
 // ------------------------------------------------------------------ 1D FFT along an axis
@@ -286,6 +484,25 @@ hipError_t launch_fourier_splat(const FilterArgs& fa, const ViewGeom* geom, cons
   return hipGetLastError();
 }
 
+hipError_t launch_fourier_op_count(const FilterArgs& fa, const ViewGeom* geom, int P, unsigned* count,
+                                  hipStream_t s) {
+  const size_t total = size_t(fa.M) * fa.M * fa.n_views;
+  hipLaunchKernelGGL(k_fop_count, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, fa, geom, P, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fourier_op_fill(const FilterArgs& fa, const ViewGeom* geom, int P, const unsigned* row_ptr,
+                                 unsigned* cursor, int2* ent, hipStream_t s) {
+  const size_t total = size_t(fa.M) * fa.M * fa.n_views;
+  hipLaunchKernelGGL(k_fop_fill, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, fa, geom, P, row_ptr, cursor,
+                     ent);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t cells = size_t(P) * P * P;
+  hipLaunchKernelGGL(k_fop_sort, dim3(unsigned((cells + 255) / 256)), dim3(256), 0, s, cells, row_ptr, ent);
+  return hipGetLastError();
+}
+
 template <int N>
 static hipError_t fft3_impl(float2* grid, float* vol, const float2* tw, hipStream_t s) {
   const dim3 blocks(unsigned(size_t(N) * N / Axis<N>::L));
@@ -297,14 +514,22 @@ static hipError_t fft3_impl(float2* grid, float* vol, const float2* tw, hipStrea
   return hipSuccess;
 }
 
-hipError_t launch_fourier_inverse(const FourierNormArgs& a, const unsigned long long* acc,
-                                  const unsigned long long* smat, const double* fix, float2* grid, const float2* tw,
-                                  float* vol, hipStream_t s) {
+hipError_t launch_fourier_gather(const FourierNormArgs& a, const unsigned* row_ptr, const int2* ent,
+                                 const float4* q, const unsigned long long* smat, float2* grid, hipStream_t s) {
+  const size_t n3 = size_t(a.N) * a.N * a.N;
+  hipLaunchKernelGGL(k_fgather, dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, s, a, row_ptr, ent, q, smat, grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_fourier_norm(const FourierNormArgs& a, const unsigned long long* acc, const unsigned long long* smat,
+                               const double* fix, float2* grid, hipStream_t s) {
   const size_t n3 = size_t(a.N) * a.N * a.N;
   hipLaunchKernelGGL(k_fnorm, dim3(unsigned((n3 + 255) / 256)), dim3(256), 0, s, a, acc, smat, fix, grid);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  switch (a.N) {
+  return hipGetLastError();
+}
+
+hipError_t launch_fourier_fft3(int N, float2* grid, const float2* tw, float* vol, hipStream_t s) {
+  switch (N) {
     case 16: return fft3_impl<16>(grid, vol, tw, s);
     case 32: return fft3_impl<32>(grid, vol, tw, s);
     case 48: return fft3_impl<48>(grid, vol, tw, s);

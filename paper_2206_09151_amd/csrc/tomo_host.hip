@@ -26,15 +26,15 @@ struct tomo_plan_s {
   float2* d_prop = nullptr;     // [npairs][M]
   float2* d_tw_fwd = nullptr;   // [M]
   float2* d_tw_inv = nullptr;   // [M]
-  float2* d_tw2_fwd = nullptr;  // [M/2] twiddles of the half-size sub-transforms (M = 256)
+  float2* d_tw2_fwd = nullptr;  // [M/2] twiddles of the half-size sub-transforms (M = 160, 192, 256)
   float2* d_tw2_inv = nullptr;  // [M/2]
-  float* d_l1part = nullptr;    // [n][4] quadrant spectral bounds (M = 256, FP16)
+  float* d_l1part = nullptr;    // [n][4] quadrant spectral bounds (M = 160, 192, 256)
   float4* d_q = nullptr;        // [n][M][M]  filtered spectra of every view
   void* d_stack = nullptr;      // [batch][M][K][M] of the plane storage type
   float* d_scale = nullptr;     // [n] FP16 plane scale per view (powers of two)
   int* d_status = nullptr;
-  // Fourier-space form (params.fourier = 1)
-  int P = 0;                            // accumulator edge: N + 1 for even N, N for odd N
+  // Fourier-space form (params.fourier = 1: gridding operator, 2: atomic splat)
+  int P = 0;                            // vertex-grid edge: N + 1 for even N, N for odd N
   float4* d_ffilt = nullptr;            // [n][M][M] filter of the Fourier-space variant built last
   int ffilt_variant = 0;                // 11, 12, or 0 before the first call
   float* d_fview = nullptr;             // [n] per-view spectral bound (power-of-two scale)
@@ -43,6 +43,9 @@ struct tomo_plan_s {
   unsigned long long* d_fsmat = nullptr;// [N][N][N] sampling matrix, 2^-32 units
   float2* d_fgrid = nullptr;            // [N][N][N] complex grid of the inverse FFT
   float2* d_tw3 = nullptr;              // [N] exp(+i 2 pi k / N)
+  unsigned* d_oprow = nullptr;          // [P^3 + 1] gridding operator row offsets
+  int2* d_opent = nullptr;              // [entries] (sample index, FP32 weight bits)
+  size_t op_entries = 0;
   bool same_R = true;
   double R0 = 0.0;
   std::string err;
@@ -88,7 +91,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->weight_mode < 0 || p->weight_mode > 2) return "weight_mode must be 0, 1 or 2";
   if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
   if (p->angle_batch < 0) return "angle_batch must be >= 0";
-  if (p->fourier != 0 && p->fourier != 1) return "fourier must be 0 or 1";
+  if (p->fourier < 0 || p->fourier > 2) return "fourier must be 0, 1 or 2";
   r->N = p->n_vox;
   r->M = p->n_pix ? p->n_pix : p->n_vox;
   if (p->n_pix < 0) return "n_pix must be >= 0";
@@ -117,7 +120,14 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->fourier) {
     const size_t n3 = size_t(r->N) * r->N * r->N, p3 = size_t(r->P) * r->P * r->P;
     r->table_bytes += size_t(r->n) * qv + n3 * 8 + size_t(r->N) * 8 + size_t(r->n) * 4 + 16;
-    r->work_bytes += p3 * 16 + n3 * 8;
+    r->work_bytes += n3 * 8;
+    if (p->fourier == 2) {
+      r->work_bytes += p3 * 16;
+    } else {
+      // operator: row offsets + at most 8 entries of 8 bytes per sample (the exact count
+      // is known after the plan's counting pass)
+      r->table_bytes += (p3 + 1) * 4 + size_t(r->n) * r->M * r->M * 8 * 8;
+    }
   }
   return "";
 }
@@ -125,7 +135,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
 std::string supported(const tomo_params* p, const Resolved& r) {
   if (!tomo::fft_supported(r.M)) {
     char b[160];
-    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128, 256)", r.M);
+    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128, 160, 192, 256)", r.M);
     return b;
   }
   if (p->fourier && !tomo::fourier_grid_supported(r.N)) {
@@ -248,6 +258,8 @@ void free_plan(tomo_plan_s* pl) {
   (void)hipFree(pl->d_fsmat);
   (void)hipFree(pl->d_fgrid);
   (void)hipFree(pl->d_tw3);
+  (void)hipFree(pl->d_oprow);
+  (void)hipFree(pl->d_opent);
 }
 
 tomo_status fail(tomo_plan_s* pl, tomo_status st, const std::string& msg) {
@@ -288,6 +300,8 @@ size_t tomo_workspace_bytes(const tomo_params* p) {
 }
 
 int32_t tomo_batch_capacity(tomo_plan_t plan) { return plan ? plan->batch : 0; }
+
+size_t tomo_fourier_entries(tomo_plan_t plan) { return plan ? plan->op_entries : 0; }
 
 size_t tomo_stack_bytes(tomo_plan_t plan, int32_t nb) {
   if (!plan || nb < 0) return 0;
@@ -460,7 +474,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       tw3[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
     }
     if ((e = dev_alloc(&pl->d_ffilt, mm * r.n)) != hipSuccess || (e = dev_alloc(&pl->d_fview, size_t(r.n))) ||
-        (e = dev_alloc(&pl->d_ffix, size_t(2))) || (e = dev_alloc(&pl->d_facc, 2 * p3)) ||
+        (e = dev_alloc(&pl->d_ffix, size_t(2))) || (p->fourier == 2 && (e = dev_alloc(&pl->d_facc, 2 * p3))) ||
         (e = dev_alloc(&pl->d_fsmat, n3)) || (e = dev_alloc(&pl->d_fgrid, n3)) ||
         (e = dev_alloc(&pl->d_tw3, size_t(r.N))))
       return cleanup_fail(e, "Fourier-space workspace allocation");
@@ -468,6 +482,45 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
         (e = hipMemsetAsync(pl->d_fsmat, 0, n3 * sizeof(unsigned long long), s)) ||
         (e = tomo::launch_sampling_splat(fa, pl->d_geom, pl->d_fsmat, s)))
       return cleanup_fail(e, "Fourier-space sampling matrix");
+    if (p->fourier == 1) {
+      // gridding operator: count, prefix sum on the host, fill, sort
+      unsigned* d_count = nullptr;
+      auto op_fail = [&](hipError_t err, const char* where) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d_count);
+        return cleanup_fail(err, where);
+      };
+      if ((e = dev_alloc(&d_count, p3)) || (e = dev_alloc(&pl->d_oprow, p3 + 1)))
+        return op_fail(e, "gridding-operator allocation");
+      if ((e = hipMemsetAsync(d_count, 0, p3 * sizeof(unsigned), s)) ||
+          (e = tomo::launch_fourier_op_count(fa, pl->d_geom, r.P, d_count, s)))
+        return op_fail(e, "gridding-operator count");
+      std::vector<unsigned> cnt(p3), row(p3 + 1);
+      if ((e = hipMemcpyAsync(cnt.data(), d_count, p3 * sizeof(unsigned), hipMemcpyDeviceToHost, s)) ||
+          (e = hipStreamSynchronize(s)))
+        return op_fail(e, "gridding-operator count read");
+      unsigned long long acc = 0;
+      for (size_t c = 0; c < p3; ++c) {
+        row[c] = unsigned(acc);
+        acc += cnt[c];
+        if (acc > 0xffffffffull) {
+          (void)hipFree(d_count);
+          free_plan(pl);
+          delete pl;
+          return perr(TOMO_EUNSUPPORTED, "gridding operator exceeds 2^32 entries; use fourier = 2");
+        }
+      }
+      row[p3] = unsigned(acc);
+      pl->op_entries = size_t(acc);
+      if ((e = dev_alloc(&pl->d_opent, std::max<size_t>(pl->op_entries, 1))) ||
+          (e = hipMemcpyAsync(pl->d_oprow, row.data(), (p3 + 1) * sizeof(unsigned), hipMemcpyHostToDevice, s)) ||
+          (e = hipMemsetAsync(d_count, 0, p3 * sizeof(unsigned), s)) ||
+          (e = hipMemsetAsync(pl->d_opent, 0, std::max<size_t>(pl->op_entries, 1) * sizeof(int2), s)) ||
+          (e = tomo::launch_fourier_op_fill(fa, pl->d_geom, r.P, pl->d_oprow, d_count, pl->d_opent, s)) ||
+          (e = hipStreamSynchronize(s)))
+        return op_fail(e, "gridding-operator fill");
+      (void)hipFree(d_count);
+    }
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup_fail(e, "plan synchronise");
   (void)hipFree(d_wtab);
@@ -556,11 +609,8 @@ tomo_status tomo_sync(tomo_plan_t pl, void* stream) {
   return TOMO_OK;
 }
 
-tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_volume, void* stream) {
-  if (!pl) return TOMO_EINVAL;
-  pl->err.clear();
-  if (!d_images || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+// Every kernel of one reconstruction, enqueued on s (no synchronisation).
+static tomo_status enqueue_reconstruct(tomo_plan_t pl, const float* d_images, float* d_volume, hipStream_t s) {
   const size_t mm = size_t(pl->M) * pl->M;
   // spectra of all views in one launch (one workgroup per view), then per batch the
   // depth planes and the gridding
@@ -581,6 +631,15 @@ tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_vol
     });
     if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
   }
+  return TOMO_OK;
+}
+
+tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_volume, void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (!d_images || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
+  tomo_status st = enqueue_reconstruct(pl, d_images, d_volume, static_cast<hipStream_t>(stream));
+  if (st != TOMO_OK) return st;
   return tomo_sync(pl, stream);
 }
 
@@ -663,10 +722,6 @@ tomo_status tomo_fourier_reconstruct(tomo_plan_t pl, const float* d_images, int3
                                 1.0 / pl->p.i_in, pl->d_fview, pl->n, s, pl->d_tw2_fwd, pl->d_l1part);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "spectra kernel");
-  e = timed(pl, 3, s, [&] {
-    return tomo::launch_fourier_splat(fa, pl->d_geom, pl->d_q, pl->d_fview, pl->d_ffix, pl->d_facc, pl->P, s);
-  });
-  if (e != hipSuccess) return dev_fail(pl, e, "Fourier splat kernels");
   tomo::FourierNormArgs na{};
   na.N = pl->N;
   na.P = pl->P;
@@ -682,11 +737,174 @@ tomo_status tomo_fourier_reconstruct(tomo_plan_t pl, const float* d_images, int3
   na.sigma = pl->p.sigma;
   na.epsilon = pl->p.epsilon;
   na.R = pl->R0;
-  e = timed(pl, 4, s, [&] {
-    return tomo::launch_fourier_inverse(na, pl->d_facc, pl->d_fsmat, pl->d_ffix, pl->d_fgrid, pl->d_tw3, d_volume, s);
-  });
-  if (e != hipSuccess) return dev_fail(pl, e, "Fourier normalise / inverse FFT kernels");
+  if (pl->p.fourier == 1) {
+    e = timed(pl, 3, s, [&] {
+      return tomo::launch_fourier_gather(na, pl->d_oprow, pl->d_opent, pl->d_q, pl->d_fsmat, pl->d_fgrid, s);
+    });
+    if (e != hipSuccess) return dev_fail(pl, e, "Fourier gridding-operator kernel");
+  } else {
+    e = timed(pl, 3, s, [&] {
+      return tomo::launch_fourier_splat(fa, pl->d_geom, pl->d_q, pl->d_fview, pl->d_ffix, pl->d_facc, pl->P, s);
+    });
+    if (e != hipSuccess) return dev_fail(pl, e, "Fourier splat kernels");
+    e = timed(pl, 4, s, [&] {
+      return tomo::launch_fourier_norm(na, pl->d_facc, pl->d_fsmat, pl->d_ffix, pl->d_fgrid, s);
+    });
+    if (e != hipSuccess) return dev_fail(pl, e, "Fourier normalise kernel");
+  }
+  e = timed(pl, 4, s, [&] { return tomo::launch_fourier_fft3(pl->N, pl->d_fgrid, pl->d_tw3, d_volume, s); });
+  if (e != hipSuccess) return dev_fail(pl, e, "Fourier inverse FFT kernels");
   return tomo_sync(pl, stream);
+}
+
+// ---------------------------------------------------------------- batched jobs
+struct tomo_batch_s {
+  std::vector<tomo_plan_t> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+};
+
+tomo_status tomo_batch_create(const tomo_plan_t* plans, const float* const* d_images, float* const* d_volumes,
+                              int32_t count, int32_t lanes, tomo_batch_t* out) {
+  g_plan_error.clear();
+  auto perr = [](tomo_status st, const std::string& m) {
+    g_plan_error = m;
+    return st;
+  };
+  if (!out || !plans || !d_images || !d_volumes) return perr(TOMO_EINVAL, "null argument");
+  if (count < 1) return perr(TOMO_EINVAL, "count must be >= 1");
+  if (lanes < 0) return perr(TOMO_EINVAL, "lanes must be >= 0");
+  for (int j = 0; j < count; ++j) {
+    if (!plans[j] || !d_images[j] || !d_volumes[j]) return perr(TOMO_EINVAL, "null plan or buffer in the job list");
+    for (int k = 0; k < j; ++k)
+      if (plans[k] == plans[j]) return perr(TOMO_EINVAL, "a plan appears twice (jobs need their own workspace)");
+  }
+  const int L = std::min<int>(count, lanes > 0 ? lanes : 8);
+  // longest job first onto the least loaded lane (work = N^3 n voxel-angle updates)
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  auto work = [&](int j) { return double(plans[j]->N) * plans[j]->N * plans[j]->N * plans[j]->n; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<double> load(L, 0.0);
+  std::vector<std::vector<int>> lane_jobs(L);
+  for (int j : order) {
+    const int l = int(std::min_element(load.begin(), load.end()) - load.begin());
+    load[l] += work(j);
+    lane_jobs[l].push_back(j);
+  }
+  hipStream_t s = nullptr;   // recording stream of the batch's own (the null stream cannot be captured)
+  std::vector<hipStream_t> ls(L, nullptr);
+  std::vector<hipEvent_t> join(L, nullptr);
+  hipEvent_t fork = nullptr;
+  std::vector<bool> timing(count);
+  auto cleanup = [&]() {
+    if (s) (void)hipStreamDestroy(s);
+    for (auto& x : ls)
+      if (x) (void)hipStreamDestroy(x);
+    for (auto& x : join)
+      if (x) (void)hipEventDestroy(x);
+    if (fork) (void)hipEventDestroy(fork);
+    for (int j = 0; j < count; ++j) plans[j]->timing = timing[j];
+  };
+  for (int j = 0; j < count; ++j) {
+    timing[j] = plans[j]->timing;
+    plans[j]->timing = false;   // no event nodes in the graph
+  }
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    e = hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join[l], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    cleanup();
+    return perr(TOMO_EDEVICE, std::string("batch set-up: ") + hipGetErrorString(e));
+  }
+  hipGraph_t graph = nullptr;
+  if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    cleanup();
+    return perr(TOMO_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+  }
+  tomo_status st = TOMO_OK;
+  e = hipEventRecord(fork, s);
+  for (int l = 0; l < L && e == hipSuccess && st == TOMO_OK; ++l) {
+    e = hipStreamWaitEvent(ls[l], fork, 0);
+    for (size_t k = 0; k < lane_jobs[l].size() && e == hipSuccess && st == TOMO_OK; ++k) {
+      const int j = lane_jobs[l][k];
+      st = enqueue_reconstruct(plans[j], d_images[j], d_volumes[j], ls[l]);
+    }
+    if (e == hipSuccess && st == TOMO_OK) e = hipEventRecord(join[l], ls[l]);
+    if (e == hipSuccess && st == TOMO_OK) e = hipStreamWaitEvent(s, join[l], 0);
+  }
+  const hipError_t ec = hipStreamEndCapture(s, &graph);
+  if (e == hipSuccess) e = ec;
+  if (st != TOMO_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    cleanup();
+    (void)hipGetLastError();
+    return perr(st != TOMO_OK ? st : TOMO_EDEVICE,
+                st != TOMO_OK ? std::string("job recording failed") : std::string("capture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    cleanup();
+    return perr(TOMO_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  cleanup();
+  auto* b = new tomo_batch_s();
+  b->plans.assign(plans, plans + count);
+  b->graph = graph;
+  b->exec = exec;
+  *out = b;
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_launch(tomo_batch_t b, void* stream) {
+  if (!b) return TOMO_EINVAL;
+  b->err.clear();
+  hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    b->err = std::string("graph launch: ") + hipGetErrorString(e);
+    return TOMO_EDEVICE;
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_sync(tomo_batch_t b, void* stream) {
+  if (!b) return TOMO_EINVAL;
+  b->err.clear();
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    b->err = std::string("synchronise: ") + hipGetErrorString(e);
+    return TOMO_EDEVICE;
+  }
+  int first_bad = -1;
+  for (size_t j = 0; j < b->plans.size(); ++j) {
+    const tomo_status st = tomo_sync(b->plans[j], nullptr);
+    if (st == TOMO_EDOMAIN && first_bad < 0) first_bad = int(j);
+    if (st != TOMO_OK && st != TOMO_EDOMAIN) {
+      b->err = "job " + std::to_string(j) + ": " + b->plans[j]->err;
+      return st;
+    }
+  }
+  if (first_bad >= 0) {
+    b->err = "job " + std::to_string(first_bad) + ": an image value was <= 0 or not finite";
+    return TOMO_EDOMAIN;
+  }
+  return TOMO_OK;
+}
+
+const char* tomo_batch_error(tomo_batch_t b) { return b ? b->err.c_str() : "batch is NULL"; }
+
+tomo_status tomo_batch_destroy(tomo_batch_t b) {
+  if (!b) return TOMO_OK;
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+  return TOMO_OK;
 }
 
 }  // extern "C"

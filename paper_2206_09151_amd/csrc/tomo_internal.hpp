@@ -26,8 +26,8 @@ int fft_threads(int M);
 
 // g = ln(I/I_in) -> 2D DFT -> (G1 G, G2 G) for nb views.  filt, q: [nb][M][M] float4.
 // scale (FP16 planes only, else NULL): per-view power-of-two plane scale, [nb].
-// M = 256 also needs the 128-point twiddles (tw_half_fwd) and a [nb][4] scratch for the
-// quadrant bounds (l1part, FP16 only).
+// M = 160, 192, 256 also need the M/2-point twiddles (tw_half_fwd) and a [nb][4] scratch for
+// the quadrant bounds (l1part, FP16 only).
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
                           float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
                           const float2* tw_half_fwd, float* l1part);
@@ -65,9 +65,19 @@ hipError_t launch_fourier_filter(const FilterArgs& fa, const ViewGeom* geom, int
 // Fixed-point unit from view_scale [n] into fix[2], clear acc [P^3][2], splat q [n][M][M] (.xy).
 hipError_t launch_fourier_splat(const FilterArgs& fa, const ViewGeom* geom, const float4* q, const float* view_scale,
                                 double* fix, unsigned long long* acc, int P, hipStream_t s);
-// Normalise into grid [N^3] (FFT order), inverse 3D FFT (tw: [N] exp(+i 2 pi k/N)), real part into vol.
-hipError_t launch_fourier_inverse(const FourierNormArgs& a, const unsigned long long* acc,
-                                  const unsigned long long* smat, const double* fix, float2* grid, const float2* tw,
-                                  float* vol, hipStream_t s);
+// Hermitian fold + normalisation of the accumulator into grid [N^3] (FFT order).
+hipError_t launch_fourier_norm(const FourierNormArgs& a, const unsigned long long* acc, const unsigned long long* smat,
+                               const double* fix, float2* grid, hipStream_t s);
+// Inverse 3D FFT of grid (tw: [N] exp(+i 2 pi k/N)), real part into vol [N^3].
+hipError_t launch_fourier_fft3(int N, float2* grid, const float2* tw, float* vol, hipStream_t s);
+// Gridding operator: per-vertex entry counts (count [P^3], zeroed), then the entries
+// (sample index, FP32 weight) at row_ptr [P^3 + 1] offsets (cursor [P^3], zeroed), sorted.
+hipError_t launch_fourier_op_count(const FilterArgs& fa, const ViewGeom* geom, int P, unsigned* count,
+                                  hipStream_t s);
+hipError_t launch_fourier_op_fill(const FilterArgs& fa, const ViewGeom* geom, int P, const unsigned* row_ptr,
+                                 unsigned* cursor, int2* ent, hipStream_t s);
+// Gather through the operator, Hermitian fold and normalisation into grid [N^3] (FFT order).
+hipError_t launch_fourier_gather(const FourierNormArgs& a, const unsigned* row_ptr, const int2* ent,
+                                 const float4* q, const unsigned long long* smat, float2* grid, hipStream_t s);
 
 }  // namespace tomo

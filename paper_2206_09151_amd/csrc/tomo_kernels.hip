@@ -40,7 +40,7 @@ template <> struct Shape<128> : Fft2Shape<128, 16, 8> {};
 
 bool fft_supported(int M) {
   switch (M) {
-    case 16: case 32: case 48: case 64: case 80: case 96: case 128: case 256: return true;
+    case 16: case 32: case 48: case 64: case 80: case 96: case 128: case 160: case 192: case 256: return true;
     default: return false;
   }
 }
@@ -54,7 +54,9 @@ int fft_threads(int M) {
     case 80: return Shape<80>::T;
     case 96: return Shape<96>::T;
     case 128: return Shape<128>::T;
-    case 256: return Shape<128>::T;   // four 128-point quadrant transforms
+    case 160: return Shape<80>::T;    // M = 2H: four H-point quadrant transforms
+    case 192: return Shape<96>::T;
+    case 256: return Shape<128>::T;
     default: return 0;
   }
 }
@@ -208,32 +210,35 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
   }
 }
 
-// ------------------------------------------------------------------ M = 256
-// A 256 x 256 block does not fit in one CU's LDS.  One radix-2 decimation in frequency
-// on both axes splits it into four independent 128 x 128 transforms:
-//   X[2k1+p1][2k2+p2] = DFT128_(n1,n2) { w^(p1 n1 + p2 n2) sum_{a,b} (-1)^(a p1 + b p2) x[n1+128a][n2+128b] }
-// with w = exp(-+ i 2 pi / 256).  Each (p1, p2) quadrant is one workgroup running the
-// 128 x 128 LDS transform; it reads its inputs from all four input quadrants and writes
+// ------------------------------------------------------------------ M = 2H (160, 192, 256)
+// A 2H x 2H block (H = 80, 96, 128) does not fit in one CU's LDS.  One radix-2 decimation in
+// frequency on both axes splits it into four independent H x H transforms:
+//   X[2k1+p1][2k2+p2] = DFT_H(n1,n2) { w^(p1 n1 + p2 n2) sum_{a,b} (-1)^(a p1 + b p2) x[n1+Ha][n2+Hb] }
+// with w = exp(-+ i 2 pi / 2H).  Each (p1, p2) quadrant is one workgroup running the
+// H x H LDS transform; it reads its inputs from all four input quadrants and writes
 // every second output row and column.  The four workgroups of a block share an XCD.
-using Half256 = Shape<128>;
 
-// g = ln(I/I_in) of a 256 x 256 image -> filtered spectra (Q1, Q2) at the quadrant's
+// g = ln(I/I_in) of a 2H x 2H image -> filtered spectra (Q1, Q2) at the quadrant's
 // output positions; l1part[view][quad] = partial spectral bound for the FP16 scale.
-__global__ __launch_bounds__(1024) void k_spectra256(const float* __restrict__ images,
-                                                     const float4* __restrict__ filt,
-                                                     const float2* __restrict__ tw256,
-                                                     const float2* __restrict__ tw128,
-                                                     float4* __restrict__ q, int* __restrict__ status,
-                                                     double inv_iin, float* __restrict__ l1part) {
-  using S = Half256;
-  constexpr int M = 256, H = 128;
+template <int H>
+__global__ __launch_bounds__(Shape<H>::T) void k_spectra2x(const float* __restrict__ images,
+                                                          const float4* __restrict__ filt,
+                                                          const float2* __restrict__ tw256,
+                                                          const float2* __restrict__ tw128,
+                                                          float4* __restrict__ q, int* __restrict__ status,
+                                                          double inv_iin, float* __restrict__ l1part) {
+  using S = Shape<H>;
+  constexpr int M = 2 * H;
   __shared__ float2 lds[(S::LDS_SPLIT_FLOATS + 1) / 2];
   __shared__ float red[S::T / 64];
   const int t = threadIdx.x;
   const int view = blockIdx.x >> 2, quad = blockIdx.x & 3;
   const int p1 = quad >> 1, p2 = quad & 1;
   const int n2 = t % H;
-  const int r = __builtin_amdgcn_readfirstlane(t / H);
+  int r_;   // uniform across a wave when H is a multiple of the wave size
+  if constexpr (H % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / H);
+  else r_ = t / H;
+  const int r = r_;
   const float* img = images + size_t(view) * M * M;
   float2 x[S::R1];
   int bad = 0;
@@ -252,7 +257,8 @@ __global__ __launch_bounds__(1024) void k_spectra256(const float* __restrict__ i
         acc += ((a & p1) ^ (b & p2)) ? -g : g;
       }
     }
-    x[m] = cscale(tw256[(p1 * n1 + p2 * n2) & (M - 1)], acc);
+    const int ti = p1 * n1 + p2 * n2;   // < 2H
+    x[m] = cscale(tw256[ti >= M ? ti - M : ti], acc);
   }
   if (bad) atomicOr(status, 1);
   fft2_block_split<S, false>(x, reinterpret_cast<float*>(lds), tw128);
@@ -296,16 +302,16 @@ __global__ void k_scale4(const float* __restrict__ l1part, float* __restrict__ s
   scale[v] = tot > 0.0f ? exp2f(14.0f - ceilf(log2f(tot))) : 1.0f;
 }
 
-// Plane pairs of 256 x 256 spectra: workgroup (view, pair, quadrant).
-template <class OutT>
-__global__ __launch_bounds__(1024) void k_planes256(const float4* __restrict__ q,
-                                                    const float2* __restrict__ prop,
-                                                    const float2* __restrict__ tw256,
-                                                    const float2* __restrict__ tw128,
-                                                    OutT* __restrict__ stack, int K, int npairs, int nb,
-                                                    const float* __restrict__ scale) {
-  using S = Half256;
-  constexpr int M = 256, H = 128;
+// Plane pairs of 2H x 2H spectra: workgroup (view, pair, quadrant).
+template <int H, class OutT>
+__global__ __launch_bounds__(Shape<H>::T) void k_planes2x(const float4* __restrict__ q,
+                                                         const float2* __restrict__ prop,
+                                                         const float2* __restrict__ tw256,
+                                                         const float2* __restrict__ tw128,
+                                                         OutT* __restrict__ stack, int K, int npairs, int nb,
+                                                         const float* __restrict__ scale) {
+  using S = Shape<H>;
+  constexpr int M = 2 * H;
   __shared__ float2 lds[(S::LDS_SPLIT_FLOATS + 1) / 2];
   const int wg = blockIdx.x;
   const int xcd = wg & 7, k = wg >> 3;
@@ -317,7 +323,10 @@ __global__ __launch_bounds__(1024) void k_planes256(const float4* __restrict__ q
   const int p1 = quad >> 1, p2 = quad & 1;
   const int t = threadIdx.x;
   const int n2 = t % H;
-  const int r = __builtin_amdgcn_readfirstlane(t / H);
+  int r_;   // uniform across a wave when H is a multiple of the wave size
+  if constexpr (H % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / H);
+  else r_ = t / H;
+  const int r = r_;
   const float4* qv = q + size_t(view) * M * M;
   const float2* pr = prop + size_t(p) * M;
   const float2 cx0 = pr[n2], cx1 = pr[n2 + H];
@@ -345,7 +354,8 @@ __global__ __launch_bounds__(1024) void k_planes256(const float4* __restrict__ q
         }
       }
     }
-    x[m] = cmul(acc, tw256[(p1 * n1 + p2 * n2) & (M - 1)]);
+    const int ti = p1 * n1 + p2 * n2;   // < 2H
+    x[m] = cmul(acc, tw256[ti >= M ? ti - M : ti]);
   }
   fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw128);
   const int sg = t % S::R2, yy = t / S::R2;
@@ -981,9 +991,16 @@ hipError_t launch_spectra(int M, const float* images, const float4* filt, const 
                           float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
                           const float2* tw_half_fwd, float* l1part) {
   if (nb <= 0) return hipSuccess;
-  if (M == 256) {
-    hipLaunchKernelGGL(k_spectra256, dim3(4 * nb), dim3(Half256::T), 0, s, images, filt, tw_fwd, tw_half_fwd, q,
-                       status, inv_iin, scale ? l1part : nullptr);
+  if (M == 160 || M == 192 || M == 256) {
+    if (M == 160)
+      hipLaunchKernelGGL(k_spectra2x<80>, dim3(4 * nb), dim3(Shape<80>::T), 0, s, images, filt, tw_fwd, tw_half_fwd,
+                         q, status, inv_iin, scale ? l1part : nullptr);
+    else if (M == 192)
+      hipLaunchKernelGGL(k_spectra2x<96>, dim3(4 * nb), dim3(Shape<96>::T), 0, s, images, filt, tw_fwd, tw_half_fwd,
+                         q, status, inv_iin, scale ? l1part : nullptr);
+    else
+      hipLaunchKernelGGL(k_spectra2x<128>, dim3(4 * nb), dim3(Shape<128>::T), 0, s, images, filt, tw_fwd,
+                         tw_half_fwd, q, status, inv_iin, scale ? l1part : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !scale) return e;
     hipLaunchKernelGGL(k_scale4, dim3((nb + 255) / 256), dim3(256), 0, s, l1part, scale, nb);
@@ -994,28 +1011,34 @@ hipError_t launch_spectra(int M, const float* images, const float4* filt, const 
 #undef CALL
 }
 
-template <class OutT>
-static hipError_t planes256_impl(const float4* q, const float2* prop, const float2* tw256, const float2* tw128,
-                                 void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s) {
+template <int H, class OutT>
+static hipError_t planes2x_impl(const float4* q, const float2* prop, const float2* tw256, const float2* tw128,
+                                void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s) {
   const int nb8 = (nb + 7) / 8;
-  hipLaunchKernelGGL(k_planes256<OutT>, dim3(8 * 4 * npairs * nb8), dim3(Half256::T), 0, s, q, prop, tw256, tw128,
-                     static_cast<OutT*>(stack), K, npairs, nb, scale);
+  hipLaunchKernelGGL((k_planes2x<H, OutT>), dim3(8 * 4 * npairs * nb8), dim3(Shape<H>::T), 0, s, q, prop, tw256,
+                     tw128, static_cast<OutT*>(stack), K, npairs, nb, scale);
   return hipGetLastError();
+}
+
+template <int H>
+static hipError_t planes2x_dtype(int dtype, const float4* q, const float2* prop, const float2* tw256,
+                                 const float2* tw128, void* stack, int K, int npairs, int nb, const float* scale,
+                                 hipStream_t s) {
+  switch (dtype) {
+    case 0: return planes2x_impl<H, float>(q, prop, tw256, tw128, stack, K, npairs, nb, nullptr, s);
+    case 1: return planes2x_impl<H, __hip_bfloat16>(q, prop, tw256, tw128, stack, K, npairs, nb, nullptr, s);
+    case 2: return planes2x_impl<H, __half>(q, prop, tw256, tw128, stack, K, npairs, nb, scale, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, const float2* tw_inv,
                          void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s,
                          const float2* tw_half_inv) {
   if (nb <= 0) return hipSuccess;
-  if (M == 256) {
-    switch (dtype) {
-      case 0: return planes256_impl<float>(q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, nullptr, s);
-      case 1:
-        return planes256_impl<__hip_bfloat16>(q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, nullptr, s);
-      case 2: return planes256_impl<__half>(q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
+  if (M == 160) return planes2x_dtype<80>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
+  if (M == 192) return planes2x_dtype<96>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
+  if (M == 256) return planes2x_dtype<128>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
 #define CALL(MM) planes_dtype<MM>(dtype, q, prop, tw_inv, stack, K, npairs, nb, scale, s)
   TOMO_DISPATCH_M(M, CALL)
 #undef CALL

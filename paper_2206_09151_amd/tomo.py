@@ -28,9 +28,11 @@ EXPORTED = [
     "tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_sync",
     "tomo_filtered_spectra", "tomo_workspace_bytes", "tomo_batch_capacity", "tomo_stack_bytes",
     "tomo_status_string", "tomo_last_error", "tomo_plan_error", "tomo_destroy",
-    "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct",
+    "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_entries",
+    "tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_error", "tomo_batch_destroy",
 ]
-KERNEL_KINDS = ("spectra", "planes", "grid", "fsplat", "finverse")
+KERNEL_KINDS = ("spectra", "planes", "grid", "fgrid", "finverse")
+FOURIER_OPERATOR, FOURIER_SPLAT = 1, 2
 EQ11, EQ12 = 11, 12
 
 
@@ -79,6 +81,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_timing_enable.argtypes = [vp, i32]
     lib.tomo_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.tomo_fourier_reconstruct.argtypes = [vp, vp, i32, ctypes.c_double, vp, vp]
+    lib.tomo_fourier_entries.argtypes = [vp]
+    lib.tomo_fourier_entries.restype = sz
+    lib.tomo_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32,
+                                      ctypes.POINTER(vp)]
+    lib.tomo_batch_launch.argtypes = [vp, vp]
+    lib.tomo_batch_sync.argtypes = [vp, vp]
+    lib.tomo_batch_error.argtypes = [vp]
+    lib.tomo_batch_error.restype = ctypes.c_char_p
+    lib.tomo_batch_destroy.argtypes = [vp]
+    for name in ("tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_sync",
                  "tomo_filtered_spectra", "tomo_destroy", "tomo_batch_capacity", "tomo_timing_enable",
                  "tomo_timing_read", "tomo_fourier_reconstruct"):
@@ -171,6 +184,11 @@ class Plan:
             raise TomoError(st, _LIB.tomo_last_error(self._h).decode())
 
     @property
+    def fourier_entries(self) -> int:
+        """Non-zero entries of the Fourier-space gridding operator (fourier = 1)."""
+        return int(_LIB.tomo_fourier_entries(self._h))
+
+    @property
     def batch(self) -> int:
         return int(_LIB.tomo_batch_capacity(self._h))
 
@@ -220,6 +238,45 @@ class Plan:
     def destroy(self):
         if getattr(self, "_h", None):
             _LIB.tomo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent reconstructions (one plan each) recorded into one HIP graph."""
+
+    def __init__(self, plans, images, volumes, lanes: int = 0):
+        if not (len(plans) == len(images) == len(volumes)) or not plans:
+            raise ValueError("plans, images and volumes must be non-empty lists of one length")
+        n = len(plans)
+        self._keep = (list(plans), list(images), list(volumes))   # buffers bound into the graph
+        hp = (ctypes.c_void_p * n)(*[p._h for p in plans])
+        hi = (ctypes.c_void_p * n)(*[_dptr(t) for t in images])
+        hv = (ctypes.c_void_p * n)(*[_dptr(t) for t in volumes])
+        out = ctypes.c_void_p()
+        st = _LIB.tomo_batch_create(hp, hi, hv, n, int(lanes), ctypes.byref(out))
+        if st != OK:
+            raise TomoError(st, _LIB.tomo_plan_error().decode())
+        self._h = out
+
+    def _check(self, st: int):
+        if st != OK:
+            raise TomoError(st, _LIB.tomo_batch_error(self._h).decode())
+
+    def launch(self, stream=None):
+        self._check(_LIB.tomo_batch_launch(self._h, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def sync(self, stream=None):
+        self._check(_LIB.tomo_batch_sync(self._h, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _LIB.tomo_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

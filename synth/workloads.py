@@ -118,3 +118,25 @@ def make_workload(w: Workload, device: str | None = None):
     else:
         raise ValueError(w.image_model)
     return ph, dirs, dist, imgs
+
+
+# Batched uneven jobs: 64 independent reconstructions in the CT/PCT regime of ct_pct_64,
+# volume edges drawn from {64, 96, 128, 160, 192} (M = K = N), view counts from
+# {60, ..., 240}; jobs 0-31 are single-axis scans over [0,180) with the axis ramp,
+# jobs 32-63 directions uniform on the sphere with sampling-matrix weights.
+BATCH_SIZES = (64, 96, 128, 160, 192)
+
+
+def batch_jobs(count: int = 64, seed: int = SEED_BASE + 3, sizes=BATCH_SIZES, views=(60, 240)):
+    """Job table of the batched workload: a list of Workloads (phantom seed per job)."""
+    rng = np.random.default_rng(seed)
+    n_vox = rng.choice(np.asarray(sizes), size=count)
+    n_views = rng.integers(views[0], views[1] + 1, size=count)
+    base = WORKLOADS["ct_pct_64"]
+    jobs = []
+    for j in range(count):
+        axis = j < count // 2
+        jobs.append(base.scaled(name=f"batch_job{j}", index=100 + j, n_vox=int(n_vox[j]), n_views=int(n_views[j]),
+                                geometry="axis" if axis else "sphere",
+                                weight_mode="ramp_axis" if axis else "sampling"))
+    return jobs

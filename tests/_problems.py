@@ -137,6 +137,22 @@ def make(name: str) -> Problem:
         lam, sig = 0.05e-10, 0.2
         imgs = _born(21, N, M, dx, lam, dirs, dist, sig, count=30)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+    if name == "m160":
+        # 160-pixel detector (quadrant path over 80-point transforms), odd K
+        n, N, M, K = 5, 40, 160, 41
+        dirs = scan.single_axis(n, 180.0, offset_deg=4.0)
+        dist = np.full(n, 70e-10)
+        lam, sig = 0.05e-10, 0.1
+        imgs = _born(23, N, M, dx, lam, dirs, dist, sig, count=24)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "m192":
+        # 192-pixel detector (quadrant path over 96-point transforms), tilted frames
+        n, N, M, K = 4, 48, 192, 48
+        dirs = scan.uniform_sphere(24, n)
+        dist = np.full(n, 70e-10)
+        lam, sig = 0.05e-10, -0.2
+        imgs = _born(24, N, M, dx, lam, dirs, dist, sig, count=24)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
     if name == "n256":
         # 256^3 Fourier grid (largest inverse-FFT size), few views
         n, N, M, K = 4, 256, 256, 8
@@ -149,4 +165,4 @@ def make(name: str) -> Problem:
 
 
 SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32",
-         "m256", "m256sph"]
+         "m256", "m256sph", "m160", "m192"]

@@ -116,11 +116,12 @@ def test_null_plan_calls_are_rejected():
 
 
 def test_fourier_params_checked():
-    st, err = _plan_status(_params(fourier=2))
+    st, err = _plan_status(_params(fourier=3))
     assert st == tomo.EINVAL and "fourier" in err
     st, err = _plan_status(_params(n_vox=44, n_pix=48, fourier=1))
     assert st == tomo.EUNSUPPORTED and "n_vox" in err
     assert tomo.workspace_bytes(_params(fourier=1)) > tomo.workspace_bytes(_params())
+    assert tomo.workspace_bytes(_params(fourier=2)) > tomo.workspace_bytes(_params())
 
 
 def test_timing_kinds_match_header():
@@ -131,3 +132,4 @@ def test_timing_kinds_match_header():
 
 def test_null_plan_fourier_call_is_rejected():
     assert tomo.lib().tomo_fourier_reconstruct(None, None, 11, 0.0, None, None) == tomo.EINVAL
+    assert tomo.lib().tomo_fourier_entries(None) == 0

@@ -26,10 +26,14 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _run(prob, variant=11, nsr=0.0, plan=None):
+MODES = [tomo.FOURIER_OPERATOR, tomo.FOURIER_SPLAT]
+MODE_IDS = ["operator", "splat"]
+
+
+def _run(prob, variant=11, nsr=0.0, plan=None, mode=tomo.FOURIER_OPERATOR):
     dev = torch.device("cuda:0")
     if plan is None:
-        plan = tomo.Plan(prob.params(fourier=1), prob.dirs, prob.dist, vaxes=prob.vaxes)
+        plan = tomo.Plan(prob.params(fourier=mode), prob.dirs, prob.dist, vaxes=prob.vaxes)
     imgs = torch.from_numpy(prob.images).to(dev)
     vol = torch.full((prob.n_vox,) * 3, float("nan"), dtype=torch.float32, device=dev)
     plan.fourier_reconstruct(imgs, vol, variant=variant, nsr=nsr)
@@ -42,11 +46,16 @@ def _oracle(prob, variant=11, nsr=0.0):
                                       prob.oracle_geometry(), vaxes=prob.vaxes, nsr=nsr, variant=variant)
 
 
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("name", FOURIER)
-def test_fourier_eq11_matches_oracle(name):
+def test_fourier_eq11_matches_oracle(name, mode):
     prob = _problems.make(name)
-    print(f"fourier eq11 {name}: N={prob.n_vox} M={prob.n_pix} n={prob.n}", flush=True)
-    got, _ = _run(prob)
+    print(f"fourier eq11 {name} mode {mode}: N={prob.n_vox} M={prob.n_pix} n={prob.n}", flush=True)
+    got, plan = _run(prob, mode=mode)
+    if mode == tomo.FOURIER_OPERATOR:
+        assert 0 < plan.fourier_entries <= 8 * prob.n * prob.n_pix ** 2
+    else:
+        assert plan.fourier_entries == 0
     want = _oracle(prob)
     assert np.all(np.isfinite(got))
     err = _rel(got, want)
@@ -54,11 +63,12 @@ def test_fourier_eq11_matches_oracle(name):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("name", ["axis32", "oddk16", "pct64", "m256"])
-def test_fourier_eq12_matches_oracle(name):
+def test_fourier_eq12_matches_oracle(name, mode):
     prob = _problems.make(name)
-    print(f"fourier eq12 {name}", flush=True)
-    got, _ = _run(prob, variant=12)
+    print(f"fourier eq12 {name} mode {mode}", flush=True)
+    got, _ = _run(prob, variant=12, mode=mode)
     err = _rel(got, _oracle(prob, variant=12))
     print(f"  rel-L2 {err:.3g}", flush=True)
     assert err <= TOL
@@ -80,12 +90,13 @@ def _nsr_in_gap(prob):
     return float(np.sqrt(ratio[i] * ratio[i + 1]))
 
 
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("name", ["axis32", "vaxes32"])
-def test_fourier_nsr_threshold_matches_oracle(name):
+def test_fourier_nsr_threshold_matches_oracle(name, mode):
     prob = _problems.make(name)
     nsr = _nsr_in_gap(prob)
-    print(f"fourier nsr {name}: nsr={nsr:.6g}", flush=True)
-    got, _ = _run(prob, nsr=nsr)
+    print(f"fourier nsr {name} mode {mode}: nsr={nsr:.6g}", flush=True)
+    got, _ = _run(prob, nsr=nsr, mode=mode)
     want = _oracle(prob, nsr=nsr)
     full = _oracle(prob)
     assert _rel(want, full) > 1e-3          # the threshold removes something
@@ -94,14 +105,22 @@ def test_fourier_nsr_threshold_matches_oracle(name):
     assert err <= TOL
 
 
-def test_fourier_is_bitwise_reproducible_and_variants_switch():
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_fourier_is_bitwise_reproducible_and_variants_switch(mode):
     prob = _problems.make("sampling32")
-    a, plan = _run(prob)
+    a, plan = _run(prob, mode=mode)
     b12, _ = _run(prob, variant=12, plan=plan)
     b, _ = _run(prob, plan=plan)
     assert np.array_equal(a, b)
     assert _rel(b12, _oracle(prob, variant=12)) <= TOL
     plan.destroy()
+
+
+def test_fourier_operator_and_splat_agree():
+    prob = _problems.make("vaxes32")
+    a, _ = _run(prob, mode=tomo.FOURIER_OPERATOR)
+    b, _ = _run(prob, mode=tomo.FOURIER_SPLAT)
+    assert _rel(a, b) <= 1e-6
 
 
 def test_fourier_errors():

@@ -79,24 +79,33 @@ def test_xray_jitter_256_view_batch_matches_oracle(xray_case, storage, bound):
     assert rel < bound, rel
 
 
-def test_dt_ewald_128_fourier_form_matches_oracle():
-    """The Fourier-space form (eq. 11 by 3D gridding) on the same full workload,
-    compared over all 128^3 voxels."""
-    from paper_2206_09151_amd import tomo
+@pytest.fixture(scope="module")
+def dt128_fourier_case():
+    """The 128^3, 180-view workload and the Fourier-space oracle over all voxels, computed once."""
     from synth import workloads
     w = workloads.WORKLOADS["dt_ewald_128"]
     ph, dirs, dist, imgs64 = workloads.make_workload(w, device="cuda")
     imgs = imgs64.astype(np.float32)
+    geo = oracle.Geometry(w.n_vox, w.M, w.K, w.voxel, w.wavelength, w.sigma, w.epsilon, ewald=w.ewald,
+                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling)
+    ref = oracle.fourier_reconstruct(imgs.astype(np.float64), dirs, dist, geo)
+    return w, dirs, dist, imgs, ref
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["operator", "splat"])
+def test_dt_ewald_128_fourier_form_matches_oracle(dt128_fourier_case, mode):
+    """The Fourier-space form (eq. 11 by 3D gridding) on the same full workload,
+    compared over all 128^3 voxels, with the gridding operator and with the splat."""
+    from paper_2206_09151_amd import tomo
+    w, dirs, dist, imgs, ref = dt128_fourier_case
     params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
                          sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
-                         weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, fourier=1)
+                         weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, fourier=mode)
     plan = tomo.Plan(params, dirs, dist)
     vol = torch.empty((w.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
     plan.fourier_reconstruct(torch.from_numpy(imgs).to("cuda:0"), vol)
     got = vol.cpu().numpy().astype(np.float64)
-    geo = oracle.Geometry(w.n_vox, w.M, w.K, w.voxel, w.wavelength, w.sigma, w.epsilon, ewald=w.ewald,
-                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling)
-    ref = oracle.fourier_reconstruct(imgs.astype(np.float64), dirs, dist, geo)
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"dt_ewald_128 Fourier-space form: rel-L2 vs FP64 = {rel:.3e}")
+    print(f"dt_ewald_128 Fourier-space form (mode {mode}): rel-L2 vs FP64 = {rel:.3e}, "
+          f"operator entries {plan.fourier_entries}")
     assert rel < 1e-5, rel

@@ -40,7 +40,7 @@ def _plan(pb, **kw):
     return tomo.Plan(pb.params(**kw), pb.dirs, pb.dist, vaxes=pb.vaxes)
 
 
-@pytest.mark.parametrize("name", ["axis32", "sphere45", "sampling32", "m96", "m256"])
+@pytest.mark.parametrize("name", ["axis32", "sphere45", "sampling32", "m96", "m256", "m160", "m192"])
 def test_filtered_spectra_match_oracle(dev, name):
     pb = _problems.make(name)
     plan = _plan(pb, angle_batch=pb.n)
@@ -57,7 +57,7 @@ def test_filtered_spectra_match_oracle(dev, name):
     assert _rel(got, P) < 2e-6, _rel(got, P)
 
 
-@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "oddk16", "m80", "m256", "m256sph"])
+@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "oddk16", "m80", "m256", "m256sph", "m160", "m192"])
 def test_plane_stacks_match_oracle(dev, name):
     pb = _problems.make(name)
     plan = _plan(pb, angle_batch=pb.n)
