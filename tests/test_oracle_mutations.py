@@ -161,3 +161,38 @@ def test_planted_fourier_mistake_is_caught(monkeypatch, name, bad, pin):
     monkeypatch.setattr(fou, name, bad)
     with pytest.raises(AssertionError):
         pin()
+
+
+# ------------------------------------------------------------------ network
+import oracle.unet as un  # noqa: E402
+import test_oracle_unet as upins  # noqa: E402
+
+_orig_conv = un.conv3d
+_orig_conv_bwd = un.conv3d_backward
+
+
+def _conv_flipped(x, w, b):
+    return _orig_conv(x, w[:, :, ::-1, ::-1, ::-1], b)          # convolution instead of correlation
+
+
+def _conv_bwd_no_input_grad_transpose(x, w, g):
+    gx, gw, gb = _orig_conv_bwd(x, w[:, :, ::-1, ::-1, ::-1], g)   # wrong tap orientation for dx
+    return gx, _orig_conv_bwd(x, w, g)[1], gb
+
+
+def _pool_bwd_unscaled(g):
+    return un.up2(g)                                            # forgot the 1/8
+
+
+UNET_MUTATIONS = [
+    ("conv3d", _conv_flipped, upins.test_conv_is_scipy_correlation_with_zero_padding),
+    ("conv3d_backward", _conv_bwd_no_input_grad_transpose, upins.test_network_gradient_matches_finite_differences),
+    ("pool2_backward", _pool_bwd_unscaled, upins.test_resampling_operators_are_adjoint),
+]
+
+
+@pytest.mark.parametrize("name,bad,pin", UNET_MUTATIONS, ids=[f"{m[0]}-{m[1].__name__}" for m in UNET_MUTATIONS])
+def test_planted_network_mistake_is_caught(monkeypatch, name, bad, pin):
+    monkeypatch.setattr(un, name, bad)
+    with pytest.raises(AssertionError):
+        pin()
