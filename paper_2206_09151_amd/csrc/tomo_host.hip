@@ -21,6 +21,7 @@ struct tomo_plan_s {
   tomo_params p{};
   int N = 0, M = 0, K = 0, n = 0, npairs = 0, batch = 0;
   bool axis_fast = false;
+  int grid_rows = 8;            // voxel rows per gridding thread (autotuned with params.tune)
   ViewGeom* d_geom = nullptr;   // [n]
   float4* d_filt = nullptr;     // [n][M][M]
   float2* d_prop = nullptr;     // [npairs][M]
@@ -92,6 +93,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
   if (p->angle_batch < 0) return "angle_batch must be >= 0";
   if (p->fourier < 0 || p->fourier > 2) return "fourier must be 0, 1 or 2";
+  if (p->tune != 0 && p->tune != 1) return "tune must be 0 or 1";
   r->N = p->n_vox;
   r->M = p->n_pix ? p->n_pix : p->n_vox;
   if (p->n_pix < 0) return "n_pix must be >= 0";
@@ -302,6 +304,8 @@ size_t tomo_workspace_bytes(const tomo_params* p) {
 int32_t tomo_batch_capacity(tomo_plan_t plan) { return plan ? plan->batch : 0; }
 
 size_t tomo_fourier_entries(tomo_plan_t plan) { return plan ? plan->op_entries : 0; }
+
+int32_t tomo_grid_rows(tomo_plan_t plan) { return plan ? plan->grid_rows : 0; }
 
 size_t tomo_stack_bytes(tomo_plan_t plan, int32_t nb) {
   if (!plan || nb < 0) return 0;
@@ -525,6 +529,47 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup_fail(e, "plan synchronise");
   (void)hipFree(d_wtab);
   (void)hipFree(d_smat);
+  d_wtab = nullptr;
+  d_smat = nullptr;
+  if (p->tune) {
+    // time the gridding kernel with 4 and 8 voxel rows per thread on a full batch of (zeroed)
+    // stacks and keep the faster; results do not depend on the choice
+    float* d_vol = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    auto tune_fail = [&](hipError_t err) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(d_vol);
+      if (ea) (void)hipEventDestroy(ea);
+      if (eb) (void)hipEventDestroy(eb);
+      return cleanup_fail(err, "gridding autotune");
+    };
+    const size_t n3 = size_t(r.N) * r.N * r.N;
+    if ((e = dev_alloc(&d_vol, n3)) || (e = hipEventCreate(&ea)) || (e = hipEventCreate(&eb)) ||
+        (e = hipMemsetAsync(pl->d_stack, 0, size_t(r.batch) * stack_view_bytes(r.M, r.K, p->plane_dtype), s)) ||
+        (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(pl->d_scale), 0x3f800000u, size_t(r.n), s)))
+      return tune_fail(e);
+    float best = 0.0f;
+    for (int rows : {8, 4}) {
+      float tot = 0.0f;
+      for (int rep = 0; rep < 4; ++rep) {
+        if ((e = hipEventRecord(ea, s)) ||
+            (e = tomo::launch_grid(pl->axis_fast, p->plane_dtype, pl->d_stack, pl->d_geom, pl->d_scale, d_vol, r.N,
+                                   r.M, r.K, r.batch, 0, p->ewald ? 0 : 1, s, rows)) ||
+            (e = hipEventRecord(eb, s)) || (e = hipEventSynchronize(eb)))
+          return tune_fail(e);
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, ea, eb))) return tune_fail(e);
+        if (rep > 0) tot += ms;   // the first launch warms up
+      }
+      if (rows == 8 || tot < best) {
+        best = tot;
+        pl->grid_rows = rows;
+      }
+    }
+    (void)hipFree(d_vol);
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+  }
   *out = pl;
   return TOMO_OK;
 }
@@ -586,7 +631,8 @@ tomo_status tomo_grid(tomo_plan_t pl, const void* d_planes, int32_t first, int32
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = timed(pl, 2, s, [&] {
     return tomo::launch_grid(pl->axis_fast, pl->p.plane_dtype, d_planes, pl->d_geom + first, pl->d_scale + first,
-                             d_volume, pl->N, pl->M, pl->K, nb, 1, pl->p.ewald ? 0 : 1, s);
+                             d_volume, pl->N, pl->M, pl->K, nb, 1, pl->p.ewald ? 0 : 1, s,
+                             pl->grid_rows);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
   return TOMO_OK;
@@ -627,7 +673,7 @@ static tomo_status enqueue_reconstruct(tomo_plan_t pl, const float* d_images, fl
     e = timed(pl, 2, s, [&] {
       return tomo::launch_grid(pl->axis_fast, pl->p.plane_dtype, pl->d_stack, pl->d_geom + first,
                                pl->d_scale + first, d_volume, pl->N, pl->M, pl->K, nb, first > 0 ? 1 : 0,
-                               pl->p.ewald ? 0 : 1, s);
+                               pl->p.ewald ? 0 : 1, s, pl->grid_rows);
     });
     if (e != hipSuccess) return dev_fail(pl, e, "grid kernel");
   }

@@ -38,8 +38,9 @@ hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, 
                          const float2* tw_half_inv);
 // Trilinear gather of nb stacks into V[N][N][N] (accumulate: V += ..., else V = ...).
 // flat: one plane without depth axis (no Ewald curvature): bilinear in the detector plane.
+// rows: voxel rows per thread (4 or 8); the per-voxel arithmetic does not depend on it.
 hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
-                       float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s);
+                       float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s, int rows);
 // Plan-time tables.
 hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const double* wtab,
                                float4* filt, hipStream_t s);

@@ -37,6 +37,8 @@ template <> struct Shape<64> : Fft2Shape<64, 16, 4> {};
 template <> struct Shape<80> : Fft2Shape<80, 20, 4> {};
 template <> struct Shape<96> : Fft2Shape<96, 24, 4> {};
 template <> struct Shape<128> : Fft2Shape<128, 16, 8> {};
+template <> struct Shape<160> : Fft2Shape<160, 40, 4> {};
+template <> struct Shape<192> : Fft2Shape<192, 48, 4> {};
 
 bool fft_supported(int M) {
   switch (M) {
@@ -54,12 +56,20 @@ int fft_threads(int M) {
     case 80: return Shape<80>::T;
     case 96: return Shape<96>::T;
     case 128: return Shape<128>::T;
-    case 160: return Shape<80>::T;    // M = 2H: four H-point quadrant transforms
-    case 192: return Shape<96>::T;
-    case 256: return Shape<128>::T;
+    case 160: return Shape<160>::T;
+    case 192: return Shape<192>::T;
+    case 256: return Shape<128>::T;   // M = 2H: four H-point quadrant transforms
     default: return 0;
   }
 }
+
+// Exchanges through half-size LDS (real, then imaginary parts): in the plane kernels
+// where the full block would leave room for only one workgroup per CU (two fit then),
+// in the spectra kernel only where the full block would not fit in one CU's LDS.
+template <int M>
+constexpr bool kSplit = (Shape<M>::LDS_BYTES > 80 * 1024);
+template <int M>
+constexpr bool kSplitSpectra = (Shape<M>::LDS_BYTES > 160 * 1024);
 
 // ------------------------------------------------------------------ K1: spectra
 template <int M>
@@ -69,7 +79,7 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
                                                          float4* __restrict__ q, int* __restrict__ status,
                                                          double inv_iin, float* __restrict__ scale) {
   using S = Shape<M>;
-  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 lds[kSplitSpectra<M> ? (S::LDS_SPLIT_FLOATS + 1) / 2 : S::LDS_ELEMS];
   __shared__ float red[S::T / 64];
   const int t = threadIdx.x;
   const int view = blockIdx.x;
@@ -87,7 +97,8 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
     x[m] = make_float2(float(g), 0.0f);
   }
   if (bad) atomicOr(status, 1);
-  fft2_block<S, false>(x, lds, tw_fwd);
+  if constexpr (kSplitSpectra<M>) fft2_block_split<S, false>(x, reinterpret_cast<float*>(lds), tw_fwd);
+  else fft2_block<S, false>(x, lds, tw_fwd);
   const int sg = t % S::R2, ky = t / S::R2;
   const size_t row = (size_t(view) * M + ky) * M;
   float l1 = 0.0f;
@@ -127,10 +138,6 @@ __global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict
 // Workgroup -> (view, pair) mapping keeps all pairs of one view on one XCD
 // (workgroups are dealt to the 8 XCDs round robin), so the view's Q block is
 // fetched into one L2 only.
-// Exchanges through half-size LDS (two workgroups per CU) where the full block would
-// leave room for only one.
-template <int M>
-constexpr bool kSplit = (Shape<M>::LDS_BYTES > 80 * 1024);
 
 // Plane storage types: FP32, BF16 (round to nearest even), FP16 (per-view power-of-two scale).
 template <class T>
@@ -984,6 +991,8 @@ static hipError_t planes_dtype(int dtype, const float4* q, const float2* prop, c
     case 80: return CALL(80);                            \
     case 96: return CALL(96);                            \
     case 128: return CALL(128);                          \
+    case 160: return CALL(160);                          \
+    case 192: return CALL(192);                          \
     default: return hipErrorInvalidValue;                \
   }
 
@@ -991,16 +1000,9 @@ hipError_t launch_spectra(int M, const float* images, const float4* filt, const 
                           float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
                           const float2* tw_half_fwd, float* l1part) {
   if (nb <= 0) return hipSuccess;
-  if (M == 160 || M == 192 || M == 256) {
-    if (M == 160)
-      hipLaunchKernelGGL(k_spectra2x<80>, dim3(4 * nb), dim3(Shape<80>::T), 0, s, images, filt, tw_fwd, tw_half_fwd,
-                         q, status, inv_iin, scale ? l1part : nullptr);
-    else if (M == 192)
-      hipLaunchKernelGGL(k_spectra2x<96>, dim3(4 * nb), dim3(Shape<96>::T), 0, s, images, filt, tw_fwd, tw_half_fwd,
-                         q, status, inv_iin, scale ? l1part : nullptr);
-    else
-      hipLaunchKernelGGL(k_spectra2x<128>, dim3(4 * nb), dim3(Shape<128>::T), 0, s, images, filt, tw_fwd,
-                         tw_half_fwd, q, status, inv_iin, scale ? l1part : nullptr);
+  if (M == 256) {
+    hipLaunchKernelGGL(k_spectra2x<128>, dim3(4 * nb), dim3(Shape<128>::T), 0, s, images, filt, tw_fwd,
+                       tw_half_fwd, q, status, inv_iin, scale ? l1part : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !scale) return e;
     hipLaunchKernelGGL(k_scale4, dim3((nb + 255) / 256), dim3(256), 0, s, l1part, scale, nb);
@@ -1036,17 +1038,13 @@ hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, 
                          void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s,
                          const float2* tw_half_inv) {
   if (nb <= 0) return hipSuccess;
-  if (M == 160) return planes2x_dtype<80>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
-  if (M == 192) return planes2x_dtype<96>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
   if (M == 256) return planes2x_dtype<128>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
 #define CALL(MM) planes_dtype<MM>(dtype, q, prop, tw_inv, stack, K, npairs, nb, scale, s)
   TOMO_DISPATCH_M(M, CALL)
 #undef CALL
 }
 
-constexpr int kYB = 8;
-
-template <class InT>
+template <int kYB, class InT>
 static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* geom, const float* scale,
                             float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
@@ -1066,15 +1064,23 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
   return hipGetLastError();
 }
 
-hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
-                       float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
+template <int YB>
+static hipError_t grid_dtype(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
+                             float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   switch (dtype) {
-    case 0: return grid_impl<float>(axis_fast, stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+    case 0: return grid_impl<YB, float>(axis_fast, stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
     case 1:
-      return grid_impl<__hip_bfloat16>(axis_fast, stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
-    case 2: return grid_impl<__half>(axis_fast, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+      return grid_impl<YB, __hip_bfloat16>(axis_fast, stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+    case 2: return grid_impl<YB, __half>(axis_fast, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
+                       float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s, int rows) {
+  if (rows == 4) return grid_dtype<4>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+  if (rows == 8) return grid_dtype<8>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_filter_table(const FilterArgs& fa, const ViewGeom* geom, const double* wtab, float4* filt,

@@ -30,6 +30,7 @@ EXPORTED = [
     "tomo_status_string", "tomo_last_error", "tomo_plan_error", "tomo_destroy",
     "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_entries",
     "tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_error", "tomo_batch_destroy",
+    "tomo_grid_rows",
 ]
 KERNEL_KINDS = ("spectra", "planes", "grid", "fgrid", "finverse")
 FOURIER_OPERATOR, FOURIER_SPLAT = 1, 2
@@ -43,7 +44,7 @@ class TomoParams(ctypes.Structure):
         ("voxel_size", ctypes.c_double), ("wavelength", ctypes.c_double), ("sigma", ctypes.c_double),
         ("epsilon", ctypes.c_double), ("eps_sampling", ctypes.c_double), ("i_in", ctypes.c_double),
         ("ewald", ctypes.c_int32), ("weight_mode", ctypes.c_int32), ("plane_dtype", ctypes.c_int32),
-        ("angle_batch", ctypes.c_int32), ("fourier", ctypes.c_int32),
+        ("angle_batch", ctypes.c_int32), ("fourier", ctypes.c_int32), ("tune", ctypes.c_int32),
         ("max_workspace_bytes", ctypes.c_size_t),
     ]
 
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_timing_enable.argtypes = [vp, i32]
     lib.tomo_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.tomo_fourier_reconstruct.argtypes = [vp, vp, i32, ctypes.c_double, vp, vp]
+    lib.tomo_grid_rows.argtypes = [vp]
+    lib.tomo_grid_rows.restype = i32
     lib.tomo_fourier_entries.argtypes = [vp]
     lib.tomo_fourier_entries.restype = sz
     lib.tomo_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32,
@@ -124,6 +127,7 @@ class Params:
     plane_dtype: int = F32
     angle_batch: int = 0
     fourier: int = 0
+    tune: int = 0
     max_workspace_bytes: int = 0
 
     def to_c(self) -> TomoParams:
@@ -131,7 +135,7 @@ class Params:
         return TomoParams(self.n_vox, self.n_pix, self.n_planes, self.n_angles, self.voxel_size,
                           self.wavelength, self.sigma, self.epsilon, self.eps_sampling, self.i_in,
                           self.ewald, mode, self.plane_dtype, self.angle_batch, self.fourier,
-                          self.max_workspace_bytes)
+                          self.tune, self.max_workspace_bytes)
 
 
 def _stream_ptr(stream) -> int | None:
@@ -182,6 +186,11 @@ class Plan:
     def _check(self, st: int):
         if st != OK:
             raise TomoError(st, _LIB.tomo_last_error(self._h).decode())
+
+    @property
+    def grid_rows(self) -> int:
+        """Voxel rows per thread of the gridding kernel (autotuned with Params.tune)."""
+        return int(_LIB.tomo_grid_rows(self._h))
 
     @property
     def fourier_entries(self) -> int:
