@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dt_ewald_128",
-                    help="dt_ewald_128 | ct_pct_64 | xray_jitter_256 | batch64 (64 uneven jobs in one graph)")
+                    help="dt_ewald_128 | ct_pct_64 | xray_jitter_256 | batch64 (64 uneven jobs in one graph) | "
+                         "unet128 (training step of the artefact-correction network at 128^3)")
     ap.add_argument("--angle-batch", type=int, default=0)
     ap.add_argument("--plane-dtype", default="f32", choices=["f32", "bf16", "fp16"],
                     help="storage type of the plane stacks (interpolation and sums stay FP32)")
@@ -128,6 +129,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         run_batch(args)
+        return
+    if args.workload == "unet128":
+        run_unet(args)
         return
     import torch
     from synth import workloads
@@ -422,6 +426,113 @@ def run_batch(args):
     }
     print(json.dumps(out), flush=True)
     batch.destroy()
+
+
+def unet_flops_per_voxel() -> float:
+    """Multiply-adds x 2 of one training step (forward, input gradients except the
+    first layer's, weight gradients) per voxel of the full-resolution volume."""
+    from synth import netinit
+    levels = [0, 0, 1, 1, 2, 2, 1, 1, 0, 0, 0]          # resolution level of each layer
+    fwd = bwd = 0.0
+    for i, ((ci, co, k), lv) in enumerate(zip(netinit.LAYERS, levels)):
+        macs = ci * co * k ** 3 / 8.0 ** lv
+        fwd += macs
+        bwd += macs * (2 if i > 0 else 1)
+    return 2.0 * (fwd + bwd)
+
+
+def run_unet(args):
+    """Training step (forward, MSE, backward, Adam) of the artefact-correction network on
+    128^3 diffraction-tomography volumes: sparse (30-view) reconstructions against dense
+    (720-view) ones of the same phantoms, both made by this library.  Reports voxels per
+    second of training, the VALU roofline, and the held-out error ratio after the run."""
+    import torch
+    from synth import netinit, workloads
+    from paper_2206_09151_amd import tomo, unet
+    base = workloads.WORKLOADS["dt_ewald_128"]
+    n = base.n_vox
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pairs = []
+    for k in range(3):
+        vols = []
+        for nv in (30, 720):
+            w = base.scaled(name=f"unet_pair{k}_{nv}", index=200 + k, n_views=nv)
+            ph, dirs, dist, im = workloads.make_workload(w, device="cuda")
+            plan = tomo.Plan(tomo.Params(n_vox=n, n_angles=nv, voxel_size=w.voxel, wavelength=w.wavelength,
+                                         sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K), dirs, dist)
+            v = torch.empty((n, n, n), device=dev)
+            plan.reconstruct(torch.from_numpy(im.astype(np.float32)).to(dev), v)
+            plan.destroy()
+            vols.append(v)
+        pairs.append(tuple(vols))
+    scale = float(torch.sqrt(torch.stack([(d * d).mean() for _, d in pairs]).mean()))
+    pairs = [(a / scale, b / scale) for a, b in pairs]
+    print(f"[bench] unet128: 3 pairs (30 vs 720 views) in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    train, held = pairs[:2], pairs[2]
+    net = unet.Net(n)
+    theta = torch.from_numpy(netinit.init_params(9)).to(dev)
+    m, v, g = torch.zeros_like(theta), torch.zeros_like(theta), torch.empty_like(theta)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    step = 0
+
+    def train_step():
+        nonlocal step
+        step += 1
+        a, b = train[(step - 1) % len(train)]
+        net.gradient(theta, a, b, g, loss)
+        net.adam(theta, g, m, v, step, 1e-3)
+
+    for _ in range(args.warmup):
+        train_step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        train_step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    y = torch.empty((n, n, n), device=dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        net.forward(theta, held[0], y)
+    torch.cuda.synchronize()
+    ms_fwd = (time.perf_counter() - t) * 1e3 / 5
+    base_err = float(((held[0] - held[1]) ** 2).mean())
+    corr_err = float(((y - held[1]) ** 2).mean())
+    flops = unet_flops_per_voxel() * n ** 3
+    achieved = flops / (ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        import oracle.unet as ou
+        crop = held[0][:32, :32, :32].cpu().numpy().astype(np.float64)
+        tgt = held[1][:32, :32, :32].cpu().numpy().astype(np.float64)
+        th = theta.cpu().numpy().astype(np.float64)
+        tc = time.perf_counter()
+        yo, cache = ou.forward(th, crop, bf16=True)
+        _, gy = ou.mse(yo, tgt)
+        ou.backward(th, cache, gy, bf16=True)
+        cs = time.perf_counter() - tc
+        cpu = {"value": 32.0 ** 3 / cs, "unit": "training voxels/s", "cores": 1, "kind": "oracle",
+               "sample": f"one forward+backward of the FP64 oracle on a 32^3 crop, {cs:.1f} s (numpy)"}
+    out = {
+        "metric": "network training voxels/s (artefact correction, forward+backward+Adam)",
+        "method": "unet_training",
+        "value": n ** 3 / (ms * 1e-3),
+        "unit": "voxels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 weights, f32 activations and sums", "data": "synthetic",
+        "config": {"workload": "unet128", "n_vox": n, "params": unet.param_count(), "sparse_views": 30,
+                   "dense_views": 720, "train_pairs": 2, "forward_ms": ms_fwd,
+                   "heldout_mse_ratio_after_run": corr_err / base_err},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK / 1e3,
+                     "unit": "TFLOP/s", "frac": round(achieved / (FP32_VALU_PEAK / 1e3), 4), "traffic": None,
+                     "note": "FP32 FMA flops of the convolutions per step / step time"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    net.destroy()
 
 
 if __name__ == "__main__":

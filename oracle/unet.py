@@ -28,8 +28,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["LAYERS", "param_count", "unpack", "conv3d", "conv3d_backward", "pool2", "pool2_backward", "up2",
-           "up2_backward", "forward", "backward", "mse", "adam_step"]
+__all__ = ["LAYERS", "param_count", "unpack", "bf16_round", "conv3d", "conv3d_backward", "pool2",
+           "pool2_backward", "up2", "up2_backward", "forward", "backward", "mse", "adam_step"]
 
 # (name, Cin, Cout, kernel edge)
 LAYERS = [("e1a", 1, 16, 3), ("e1b", 16, 16, 3), ("e2a", 16, 32, 3), ("e2b", 32, 32, 3),
@@ -41,12 +41,22 @@ def param_count():
     return sum(co * ci * k ** 3 + co for _, ci, co, k in LAYERS)
 
 
-def unpack(theta):
-    """{name: (w [Cout][Cin][k][k][k], b [Cout])} views of the flat parameter vector."""
+def bf16_round(a):
+    """Nearest bfloat16 (8 significant bits, ties to the even significand) of float32 values."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unpack(theta, bf16=False):
+    """{name: (w [Cout][Cin][k][k][k], b [Cout])} of the flat parameter vector; with bf16
+    the weights are their BF16 roundings (the precision the network's convolutions use)."""
     out, off = {}, 0
     for name, ci, co, k in LAYERS:
         nw = co * ci * k ** 3
         w = theta[off:off + nw].reshape(co, ci, k, k, k)
+        if bf16:
+            w = bf16_round(w)
         off += nw
         out[name] = (w, theta[off:off + co])
         off += co
@@ -108,9 +118,9 @@ def _relu(z):
 
 
 # ----------------------------------------------------------------------------- network
-def forward(theta, x):
+def forward(theta, x, bf16=False):
     """y = x + f(x) for one volume x [n][n][n]; returns (y, cache)."""
-    p = unpack(theta)
+    p = unpack(theta, bf16)
     a = {}
     a["x"] = x[None]
     a["e1a"] = _relu(conv3d(a["x"], *p["e1a"]))
@@ -131,9 +141,10 @@ def forward(theta, x):
     return y, a
 
 
-def backward(theta, cache, gy):
-    """Gradient of sum(gy * y) with respect to the parameter vector (and to x)."""
-    p = unpack(theta)
+def backward(theta, cache, gy, bf16=False):
+    """Gradient of sum(gy * y) with respect to the parameter vector (and to x); with bf16
+    the weights are rounded as in forward (gradients are taken at the rounded weights)."""
+    p = unpack(theta, bf16)
     a = cache
     grads = {}
 

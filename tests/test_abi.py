@@ -133,3 +133,24 @@ def test_timing_kinds_match_header():
 def test_null_plan_fourier_call_is_rejected():
     assert tomo.lib().tomo_fourier_reconstruct(None, None, 11, 0.0, None, None) == tomo.EINVAL
     assert tomo.lib().tomo_fourier_entries(None) == 0
+
+
+def test_network_header_and_library_agree():
+    text = open(os.path.join(ROOT, "include", "tomo_unet.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(tomo_unet_[a-z_]+)\s*\(", text)))
+    from paper_2206_09151_amd import unet
+    assert declared == sorted(unet.EXPORTED)
+    lib = tomo.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    from oracle import unet as ounet
+    assert unet.param_count() == ounet.param_count()
+
+
+def test_network_rejects_bad_sizes():
+    from paper_2206_09151_amd import unet
+    for n in (6, 4, 260):
+        with pytest.raises(tomo.TomoError) as ei:
+            unet.Net(n)
+        assert ei.value.status == tomo.EINVAL and "multiple of 4" in str(ei.value)

@@ -104,3 +104,18 @@ def test_first_adam_step_moves_by_lr_times_sign():
     th = RNG.standard_normal(50)
     new, m, v = unet.adam_step(th, g, np.zeros(50), np.zeros(50), 1, lr=1e-3, eps=0.0)
     np.testing.assert_allclose(th - new, 1e-3 * np.sign(g), rtol=1e-12)
+
+
+def test_bf16_rounding_is_nearest_with_ties_to_even():
+    one = 1.0
+    cases = {one + 2.0 ** -8: 1.0, one + 3 * 2.0 ** -8: one + 2.0 ** -6, one + 2.0 ** -7: one + 2.0 ** -7,
+             -(one + 2.0 ** -8 + 2.0 ** -12): -(one + 2.0 ** -7), 3.0: 3.0}
+    for a, want in cases.items():
+        assert unet.bf16_round(np.array([a], np.float32))[0] == want, a
+    # random values: the result has 8 significant bits and no 8-bit value is closer
+    a = (RNG.standard_normal(2000) * 10.0 ** RNG.integers(-6, 6, 2000)).astype(np.float32)
+    r = unet.bf16_round(a)
+    e = np.floor(np.log2(np.abs(a.astype(np.float64))))
+    ulp = 2.0 ** (e - 7)
+    assert np.all(np.abs(r / ulp - np.round(r / ulp)) < 1e-9)             # on the 8-bit grid (or the next binade)
+    assert np.all(np.abs(r - a) <= 0.5 * ulp * (1 + 1e-12))
