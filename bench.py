@@ -326,7 +326,7 @@ def run_batch(args):
     for w, (dirs, dist, im) in zip(jobs, data):
         params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
                              sigma=w.sigma, epsilon=w.epsilon, ewald=w.ewald, weight_mode=w.weight_mode,
-                             eps_sampling=w.eps_sampling, i_in=w.i_in)
+                             eps_sampling=w.eps_sampling, i_in=w.i_in, tune=1)
         plans.append(tomo.Plan(params, dirs, dist))
         imgs.append(torch.from_numpy(im).to(dev))
         vols.append(torch.empty((w.n_vox,) * 3, dtype=torch.float32, device=dev))

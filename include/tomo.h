@@ -101,8 +101,10 @@ typedef struct {
                              per non-zero trilinear weight, at most 64 n M^2 bytes), used as a
                              gather per call; 2 a per-call splat with 64-bit integer atomics
                              (16 (N+1)^3 bytes) */
-  int32_t tune;           /* 1: time the gridding kernel with 4 and 8 voxel rows per thread
-                             on a batch of stacks at plan time and keep the faster; 0: 8 rows.
+  int32_t tune;           /* 1: time the gridding variants on a batch of stacks at plan time
+                             and keep the fastest: 4 or 8 voxel rows per thread, and for
+                             views in general frames also 8x8x8 cubic tiles; 0: 8 rows;
+                             2: cubic tiles for general frames (8 rows for single-axis plans).
                              Single-axis plans give identical results either way; for other
                              frames the choice moves only the FP32 rounding */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
@@ -218,7 +220,7 @@ tomo_status tomo_batch_sync(tomo_batch_t batch, void* stream);
 const char* tomo_batch_error(tomo_batch_t batch);
 tomo_status tomo_batch_destroy(tomo_batch_t batch);
 
-/* Voxel rows per thread of the plan's gridding kernel (4 or 8; see tune). */
+/* Gridding variant of the plan: voxel rows per thread (4 or 8), or 0 for cubic tiles (see tune). */
 int32_t tomo_grid_rows(tomo_plan_t plan);
 
 /* Non-zero entries of the plan's Fourier-space gridding operator (0 unless fourier = 1). */

@@ -21,7 +21,7 @@ struct tomo_plan_s {
   tomo_params p{};
   int N = 0, M = 0, K = 0, n = 0, npairs = 0, batch = 0;
   bool axis_fast = false;
-  int grid_rows = 8;            // voxel rows per gridding thread (autotuned with params.tune)
+  int grid_rows = 8;            // gridding variant: 8 or 4 voxel rows per thread, 0 cubic tiles (params.tune)
   ViewGeom* d_geom = nullptr;   // [n]
   float4* d_filt = nullptr;     // [n][M][M]
   float2* d_prop = nullptr;     // [npairs][M]
@@ -93,7 +93,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
   if (p->angle_batch < 0) return "angle_batch must be >= 0";
   if (p->fourier < 0 || p->fourier > 2) return "fourier must be 0, 1 or 2";
-  if (p->tune != 0 && p->tune != 1) return "tune must be 0 or 1";
+  if (p->tune < 0 || p->tune > 2) return "tune must be 0, 1 or 2";
   r->N = p->n_vox;
   r->M = p->n_pix ? p->n_pix : p->n_vox;
   if (p->n_pix < 0) return "n_pix must be >= 0";
@@ -531,7 +531,8 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   (void)hipFree(d_smat);
   d_wtab = nullptr;
   d_smat = nullptr;
-  if (p->tune) {
+  if (p->tune == 2 && !pl->axis_fast) pl->grid_rows = 0;
+  if (p->tune == 1) {
     // time the gridding kernel with 4 and 8 voxel rows per thread on a full batch of (zeroed)
     // stacks and keep the faster; results do not depend on the choice
     float* d_vol = nullptr;
@@ -549,7 +550,8 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
         (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(pl->d_scale), 0x3f800000u, size_t(r.n), s)))
       return tune_fail(e);
     float best = 0.0f;
-    for (int rows : {8, 4}) {
+    for (int rows : {8, 4, 0}) {
+      if (rows == 0 && pl->axis_fast) continue;   // the cubic tiles serve general frames only
       float tot = 0.0f;
       for (int rep = 0; rep < 4; ++rep) {
         if ((e = hipEventRecord(ea, s)) ||

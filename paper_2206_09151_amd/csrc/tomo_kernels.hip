@@ -777,6 +777,170 @@ __global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
   }
 }
 
+// General view frames, cubic tiles: 8 x 8 x 8 voxels, two per thread (iz and iz + 4).
+// The voxel centres of a cube of edge 8 span at most 7 (|a_x| + |a_y| + |a_z|) <= 7 sqrt(3)
+// < 12.2 along any unit vector a, so with the taps and the floor of the origin a box of
+// 16 rows x 16 planes x CW columns (column start rounded down to a 16-byte boundary) holds
+// the footprint for every view: no fallback path, whatever the orientation.
+template <class InT>
+struct CubeBox;
+template <>
+struct CubeBox<float> {
+  static constexpr int VEC = 4, CW = 20, CP = 20;
+};
+template <>
+struct CubeBox<__hip_bfloat16> {
+  static constexpr int VEC = 8, CW = 24, CP = 24;
+};
+template <>
+struct CubeBox<__half> {
+  static constexpr int VEC = 8, CW = 24, CP = 24;
+};
+constexpr int CB_E = 8;    // voxel tile edge
+constexpr int CB_R = 16;   // rows and planes staged per view
+
+template <class InT>
+__global__ __launch_bounds__(256) void k_grid_cube(const InT* __restrict__ stack,
+                                                   const ViewGeom* __restrict__ geom,
+                                                   const float* __restrict__ scale,
+                                                   float* __restrict__ vol, int N, int M, int K,
+                                                   int nb, int accumulate, int flat) {
+  using B = CubeBox<InT>;
+  constexpr int VEC = B::VEC, CW = B::CW, CP = B::CP;
+  constexpr int QN = CW / VEC;
+  constexpr int NE = CB_R * CB_R * QN;
+  constexpr int PER = (NE + 255) / 256;
+  __shared__ float box[CB_R][CB_R][CP];
+  // tiles of one XCD are consecutive in x, then y, then z (neighbours share stack rows in L2)
+  const int ntc = (N + CB_E - 1) / CB_E;
+  const int tiles = ntc * ntc * ntc;
+  const int per = (tiles + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= tiles) return;                           // uniform
+  const int tx0 = (tile % ntc) * CB_E, ty0 = ((tile / ntc) % ntc) * CB_E, tz0 = (tile / (ntc * ntc)) * CB_E;
+  const int ix = tx0 + (threadIdx.x % CB_E), iy = ty0 + (threadIdx.x / CB_E) % CB_E;
+  const int iz0 = tz0 + int(threadIdx.x) / (CB_E * CB_E);
+  const bool live0 = ix < N && iy < N && iz0 < N, live1 = ix < N && iy < N && iz0 + 4 < N;
+  const double c = 0.5 * (N - 1);
+  const double rx = ix - c, ry = iy - c, rz0 = iz0 - c;
+  const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
+  const size_t plane_sz = size_t(K) * M;
+  const bool vec = (M % VEC) == 0;
+  const double lo[3] = {tx0 - c, ty0 - c, tz0 - c};
+  const double hi[3] = {tx0 + CB_E - 1 - c, ty0 + CB_E - 1 - c, tz0 + CB_E - 1 - c};
+
+  auto origin = [&](int n, int& r0, int& p0, int& c0) {
+    const ViewGeom& g = geom[n];
+    double cmin = hm, rmin = hm, pmin = hk;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cmin += fmin(g.u[a] * lo[a], g.u[a] * hi[a]);
+      rmin += fmin(g.v[a] * lo[a], g.v[a] * hi[a]);
+      pmin += fmin(g.d[a] * lo[a], g.d[a] * hi[a]);
+    }
+    c0 = int(floor(cmin)) & ~(VEC - 1);
+    r0 = int(floor(rmin));
+    p0 = flat ? 0 : int(floor(pmin));
+  };
+  auto fetch = [&](int n, int r0, int p0, int c0, uint4 (&v)[PER], unsigned& valid) {
+    const InT* vbase = stack + size_t(n) * plane_sz * M;
+    valid = 0u;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int q = e % QN, pl = (e / QN) % CB_R, j = e / (QN * CB_R);
+      const int row = r0 + j, pp = p0 + pl, cc = c0 + VEC * q;
+      const bool ok = e < NE && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) && cc >= 0 && cc < M;
+      valid |= ok ? (1u << i) : 0u;
+      const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
+      if (vec) {
+        const int ccc = min(max(cc, 0), M - VEC);
+        v[i] = *reinterpret_cast<const uint4*>(vbase + (size_t(rowc) * K + ppc) * M + ccc);
+      } else {
+        const InT* src = vbase + (size_t(rowc) * K + ppc) * M;
+        Chunk16 x;
+#pragma unroll
+        for (int kk = 0; kk < VEC; ++kk) {
+          const int ce = min(max(cc + kk, 0), M - 1);
+          const bool ek = unsigned(cc + kk) < unsigned(M);
+          if constexpr (VEC == 4) x.f[kk] = ek ? from_store<InT>(src[ce]) : 0.0f;
+          else x.h[kk] = ek ? reinterpret_cast<const unsigned short*>(src)[ce] : (unsigned short)0;
+        }
+        v[i] = x.u;
+        if (e < NE && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K)) valid |= (1u << i);
+      }
+    }
+  };
+  auto stage = [&](const uint4 (&v)[PER], unsigned valid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NE) {
+        const int q = e % QN, pl = (e / QN) % CB_R, j = e / (QN * CB_R);
+        Chunk16 x;
+        x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
+        float* dst = &box[j][pl][VEC * q];
+#pragma unroll
+        for (int h = 0; h < VEC; h += 4)
+          *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
+                                                            chunk_value<InT>(x, h + 2), chunk_value<InT>(x, h + 3));
+      }
+    }
+  };
+
+  float acc0 = 0.0f, acc1 = 0.0f;
+  uint4 buf[PER];
+  unsigned valid = 0u;
+  int r0 = 0, p0 = 0, c0 = 0;
+  if (nb > 0) {
+    origin(0, r0, p0, c0);
+    fetch(0, r0, p0, c0, buf, valid);
+  }
+  for (int n = 0; n < nb; ++n) {
+    const int rr0 = r0, pp0 = p0, cc0 = c0;
+    __syncthreads();
+    stage(buf, valid);
+    __syncthreads();
+    if (n + 1 < nb) {
+      origin(n + 1, r0, p0, c0);
+      fetch(n + 1, r0, p0, c0, buf, valid);
+    }
+    const ViewGeom& g = geom[n];
+    const float inv = scale ? 1.0f / scale[n] : 1.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double rz = rz0 + 4 * h;
+      // box-local coordinates (FP64, rounded once); fmax guards a rounding-level dip below the origin
+      const float fc = float(fmax(g.u[0] * rx + g.u[1] * ry + g.u[2] * rz + hm - cc0, 0.0));
+      const float fr = float(fmax(g.v[0] * rx + g.v[1] * ry + g.v[2] * rz + hm - rr0, 0.0));
+      const float fp = flat ? 0.0f : float(fmax(g.d[0] * rx + g.d[1] * ry + g.d[2] * rz + hk - pp0, 0.0));
+      const float fc0 = floorf(fc), fr0 = floorf(fr), fp0 = floorf(fp);
+      const float tc = fc - fc0, tr = fr - fr0, tp = flat ? 0.0f : fp - fp0;
+      const int lc = int(fc0), lr = int(fr0), lp = int(fp0);
+      const int lp1 = flat ? lp : lp + 1;
+      const float* a0 = &box[lr][lp][lc];
+      const float* a1 = &box[lr][lp1][lc];
+      const float* b0 = &box[lr + 1][lp][lc];
+      const float* b1 = &box[lr + 1][lp1][lc];
+      const float v0 = a0[0] + tc * (a0[1] - a0[0]);
+      const float v1 = a1[0] + tc * (a1[1] - a1[0]);
+      const float v2 = b0[0] + tc * (b0[1] - b0[0]);
+      const float v3 = b1[0] + tc * (b1[1] - b1[0]);
+      const float add = inv * ((1.0f - tr) * ((1.0f - tp) * v0 + tp * v1) + tr * ((1.0f - tp) * v2 + tp * v3));
+      if (h == 0) acc0 += add;
+      else acc1 += add;
+    }
+  }
+  if (live0) {
+    float* dst = vol + (size_t(iz0) * N + iy) * N + ix;
+    *dst = accumulate ? *dst + acc0 : acc0;
+  }
+  if (live1) {
+    float* dst = vol + (size_t(iz0 + 4) * N + iy) * N + ix;
+    *dst = accumulate ? *dst + acc1 : acc1;
+  }
+}
+
 // General view frames: full trilinear interpolation per voxel.  Each thread owns
 // voxel column (ix, iy) and ZB consecutive iz.
 template <int ZB, class InT>
@@ -1076,8 +1240,26 @@ static hipError_t grid_dtype(bool axis_fast, int dtype, const void* stack, const
   }
 }
 
+template <class InT>
+static hipError_t grid_cube_impl(const void* stack, const ViewGeom* geom, const float* scale, float* vol, int N,
+                                 int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
+  const int ntc = (N + CB_E - 1) / CB_E;
+  const int per = (ntc * ntc * ntc + 7) / 8;
+  hipLaunchKernelGGL(k_grid_cube<InT>, dim3(unsigned(8 * per)), dim3(256), 0, s, static_cast<const InT*>(stack),
+                     geom, scale, vol, N, M, K, nb, accumulate, flat);
+  return hipGetLastError();
+}
+
 hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
                        float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s, int rows) {
+  if (rows == 0 && !axis_fast) {
+    switch (dtype) {
+      case 0: return grid_cube_impl<float>(stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+      case 1: return grid_cube_impl<__hip_bfloat16>(stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+      case 2: return grid_cube_impl<__half>(stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (rows == 4) return grid_dtype<4>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   if (rows == 8) return grid_dtype<8>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   return hipErrorInvalidValue;
