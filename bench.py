@@ -42,6 +42,8 @@ def parse():
                     help="dt_ewald_128 | ct_pct_64 | xray_jitter_256 | batch64 (64 uneven jobs in one graph) | "
                          "unet128 (training step of the artefact-correction network at 128^3)")
     ap.add_argument("--angle-batch", type=int, default=0)
+    ap.add_argument("--tune", type=int, default=1, choices=[0, 1, 2],
+                    help="gridding variant: 0 fixed, 1 autotuned at plan time (default), 2 cubic tiles")
     ap.add_argument("--plane-dtype", default="f32", choices=["f32", "bf16", "fp16"],
                     help="storage type of the plane stacks (interpolation and sums stay FP32)")
     ap.add_argument("--cpu-voxels", type=int, default=0,
@@ -150,6 +152,7 @@ def main():
                          sigma=w.sigma, epsilon=w.epsilon, n_pix=w.M, n_planes=w.K, ewald=w.ewald,
                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in,
                          angle_batch=args.angle_batch, fourier=args.fourier_mode if args.method == "fourier" else 0,
+                         tune=args.tune,
                          plane_dtype={"f32": tomo.F32, "bf16": tomo.BF16, "fp16": tomo.F16}[args.plane_dtype])
     stream = torch.cuda.current_stream()
     plan = tomo.Plan(params, dirs, dist, stream=stream)
@@ -286,7 +289,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_vox": w.n_vox, "n_pix": w.M, "n_planes": w.K,
+        "config": {"workload": w.name, "n_vox": w.n_vox, "n_pix": w.M, "n_planes": w.K, "grid_variant": plan.grid_rows,
                    "plane_storage": args.plane_dtype,
                    "n_views": w.n_views, "ewald": w.ewald, "weight_mode": w.weight_mode,
                    "angle_batch": batch, "updates_per_step": updates,
