@@ -44,7 +44,8 @@ struct tomo_unet_s {
   float *g_bb = nullptr, *g_ba = nullptr, *g_p2 = nullptr, *g_e2b = nullptr, *g_e2a = nullptr, *g_p1 = nullptr;
   float *g_e1b = nullptr, *g_e1a = nullptr;
   __hip_bfloat16* wbf = nullptr;
-  float *pw = nullptr, *pb = nullptr;
+  unsigned short *wf = nullptr, *wd = nullptr;   // matrix-core weight layouts (same offsets as wbf)
+  float *pw = nullptr, *pb = nullptr, *q = nullptr;
   double* part = nullptr;
   std::vector<void*> allocs;
   std::string err;
@@ -71,6 +72,12 @@ tomo_status fail(tomo_unet_s* u, hipError_t e, const char* where) {
 }
 
 const __hip_bfloat16* W(const tomo_unet_s* u, int l) { return u->wbf + u->off[l]; }
+bool has_layout(int l) {
+  const Layer& L = kLayers[l];
+  return unet::mfma_layer(L.ks, L.cin, L.cout) && L.cin % 16 == 0;
+}
+const unsigned short* WF(const tomo_unet_s* u, int l) { return has_layout(l) ? u->wf + u->off[l] : nullptr; }
+const unsigned short* WD(const tomo_unet_s* u, int l) { return has_layout(l) ? u->wd + u->off[l] : nullptr; }
 const float* B(const tomo_unet_s* u, const float* th, int l) { return th + u->off[l] + weights_of(l); }
 
 hipError_t forward(tomo_unet_s* u, const float* th, const float* x, float* y, hipStream_t s) {
@@ -78,33 +85,37 @@ hipError_t forward(tomo_unet_s* u, const float* th, const float* x, float* y, hi
   hipError_t e;
   const int P = u->off[kNL];
   if ((e = unet::round_bf16(th, u->wbf, P, s))) return e;
+  for (int l = 0; l < kNL; ++l)
+    if (has_layout(l) &&
+        (e = unet::weight_layout(W(u, l), kLayers[l].cout, kLayers[l].cin, u->wf + u->off[l], u->wd + u->off[l], s)))
+      return e;
   float* e1b = u->c1 + 32 * u->v1;   // the skip half of the level-1 concatenation
   float* e2b = u->c2 + 64 * u->v2;
-  if ((e = unet::conv_fwd(3, x, 1, nullptr, 1, W(u, E1A), B(u, th, E1A), u->e1a, 16, n, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->e1a, 16, nullptr, 16, W(u, E1B), B(u, th, E1B), e1b, 16, n, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, x, 1, nullptr, 1, W(u, E1A), WF(u, E1A), B(u, th, E1A), u->e1a, 16, n, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->e1a, 16, nullptr, 16, W(u, E1B), WF(u, E1B), B(u, th, E1B), e1b, 16, n, 1, nullptr, s))) return e;
   if ((e = unet::pool2(e1b, u->p1, 16, n, s))) return e;
-  if ((e = unet::conv_fwd(3, u->p1, 16, nullptr, 16, W(u, E2A), B(u, th, E2A), u->e2a, 32, h, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->e2a, 32, nullptr, 32, W(u, E2B), B(u, th, E2B), e2b, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->p1, 16, nullptr, 16, W(u, E2A), WF(u, E2A), B(u, th, E2A), u->e2a, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->e2a, 32, nullptr, 32, W(u, E2B), WF(u, E2B), B(u, th, E2B), e2b, 32, h, 1, nullptr, s))) return e;
   if ((e = unet::pool2(e2b, u->p2, 32, h, s))) return e;
-  if ((e = unet::conv_fwd(3, u->p2, 32, nullptr, 32, W(u, BA), B(u, th, BA), u->ba, 64, q, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->ba, 64, nullptr, 64, W(u, BB), B(u, th, BB), u->bb, 64, q, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->p2, 32, nullptr, 32, W(u, BA), WF(u, BA), B(u, th, BA), u->ba, 64, q, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->ba, 64, nullptr, 64, W(u, BB), WF(u, BB), B(u, th, BB), u->bb, 64, q, 1, nullptr, s))) return e;
   if ((e = unet::up2(u->bb, u->c2, 64, h, s))) return e;
-  if ((e = unet::conv_fwd(3, u->c2, 96, nullptr, 96, W(u, D2A), B(u, th, D2A), u->d2a, 32, h, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->d2a, 32, nullptr, 32, W(u, D2B), B(u, th, D2B), u->d2b, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->c2, 96, nullptr, 96, W(u, D2A), WF(u, D2A), B(u, th, D2A), u->d2a, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->d2a, 32, nullptr, 32, W(u, D2B), WF(u, D2B), B(u, th, D2B), u->d2b, 32, h, 1, nullptr, s))) return e;
   if ((e = unet::up2(u->d2b, u->c1, 32, n, s))) return e;
-  if ((e = unet::conv_fwd(3, u->c1, 48, nullptr, 48, W(u, D1A), B(u, th, D1A), u->d1a, 16, n, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->d1a, 16, nullptr, 16, W(u, D1B), B(u, th, D1B), u->d1b, 16, n, 1, nullptr, s))) return e;
-  return unet::conv_fwd(1, u->d1b, 16, nullptr, 16, W(u, OUT), B(u, th, OUT), y, 1, n, 0, x, s);
+  if ((e = unet::conv_fwd(3, u->c1, 48, nullptr, 48, W(u, D1A), WF(u, D1A), B(u, th, D1A), u->d1a, 16, n, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->d1a, 16, nullptr, 16, W(u, D1B), WF(u, D1B), B(u, th, D1B), u->d1b, 16, n, 1, nullptr, s))) return e;
+  return unet::conv_fwd(1, u->d1b, 16, nullptr, 16, W(u, OUT), WF(u, OUT), B(u, th, OUT), y, 1, n, 0, x, s);
 }
 
 // weight + bias gradient of layer l into grad, and (optionally) its input gradient
 hipError_t layer_back(tomo_unet_s* u, int l, const float* in, const float* g, const float* yout, int n, float* grad,
                       float* gx0, int c0, float* gx1, hipStream_t s) {
   const Layer& L = kLayers[l];
-  hipError_t e = unet::conv_bwd_w(L.ks, in, L.cin, nullptr, L.cin, g, yout, L.cout, n, u->pw, u->pb,
+  hipError_t e = unet::conv_bwd_w(L.ks, in, L.cin, nullptr, L.cin, g, yout, L.cout, n, u->pw, u->pb, u->q,
                                   grad + u->off[l], grad + u->off[l] + weights_of(l), s);
   if (e != hipSuccess || !gx0) return e;
-  return unet::conv_bwd_data(L.ks, g, yout, L.cout, W(u, l), gx0, c0, gx1, L.cin, n, s);
+  return unet::conv_bwd_data(L.ks, g, yout, L.cout, W(u, l), WD(u, l), gx0, c0, gx1, L.cin, n, s);
 }
 
 hipError_t backward(tomo_unet_s* u, const float* x, float* grad, hipStream_t s) {
@@ -151,9 +162,16 @@ tomo_status tomo_unet_create(int32_t n, tomo_unet_t* out) {
   u->v2 = u->v1 / 8;
   u->v3 = u->v2 / 8;
   u->off = offsets();
-  size_t max_w = 0;
-  for (int l = 0; l < kNL; ++l) max_w = std::max<size_t>(max_w, size_t(weights_of(l)));
-  const size_t chunks = size_t(unet::weight_grad_chunks(n));
+  // weight-gradient workspace: the largest any layer needs at its level's edge
+  size_t max_pw = 0, max_pb = 0, max_q = 0;
+  const int level_n[kNL] = {n, n, n / 2, n / 2, n / 4, n / 4, n / 2, n / 2, n, n, n};
+  for (int l = 0; l < kNL; ++l) {
+    size_t a, b, c;
+    unet::wgrad_workspace(kLayers[l].ks, kLayers[l].cin, kLayers[l].cout, level_n[l], a, b, c);
+    max_pw = std::max(max_pw, a);
+    max_pb = std::max(max_pb, b);
+    max_q = std::max(max_q, c);
+  }
   const size_t v1 = u->v1, v2 = u->v2, v3 = u->v3;
   hipError_t e;
   if ((e = grab(u, &u->e1a, 16 * v1)) || (e = grab(u, &u->c1, 48 * v1)) || (e = grab(u, &u->p1, 16 * v2)) ||
@@ -166,7 +184,8 @@ tomo_status tomo_unet_create(int32_t n, tomo_unet_t* out) {
       (e = grab(u, &u->g_ba, 64 * v3)) || (e = grab(u, &u->g_p2, 32 * v3)) || (e = grab(u, &u->g_e2b, 32 * v2)) ||
       (e = grab(u, &u->g_e2a, 32 * v2)) || (e = grab(u, &u->g_p1, 16 * v2)) || (e = grab(u, &u->g_e1b, 16 * v1)) ||
       (e = grab(u, &u->g_e1a, 16 * v1)) || (e = grab(u, &u->wbf, size_t(u->off[kNL]))) ||
-      (e = grab(u, &u->pw, chunks * max_w)) || (e = grab(u, &u->pb, chunks * 64)) ||
+      (e = grab(u, &u->wf, size_t(u->off[kNL]))) || (e = grab(u, &u->wd, size_t(u->off[kNL]))) ||
+      (e = grab(u, &u->pw, max_pw)) || (e = grab(u, &u->pb, max_pb)) || (e = grab(u, &u->q, max_q)) ||
       (e = grab(u, &u->part, (v1 + 255) / 256))) {
     release(u);
     delete u;

@@ -7,16 +7,27 @@
 
 namespace unet {
 
-// out[co] = act(b + conv_ks(in)) (+ res), input channels [0, c0) from x0 and [c0, cin) from x1.
+// Whether a layer runs on the matrix-core kernels (3x3x3, cout in {16, 32, 64}, cin a
+// multiple of 16 up to 96, or cin == 1 for the weight gradient).
+bool mfma_layer(int ks, int cin, int cout);
+// BF16 weight layouts of a matrix-core layer (cin and cout multiples of 16): wf for the
+// forward, wd (taps reversed) for the input gradient; each holds cout * cin * 27 values.
+hipError_t weight_layout(const __hip_bfloat16* w, int cout, int cin, unsigned short* wf, unsigned short* wd,
+                         hipStream_t s);
+// out[co] = act(b + conv_ks(in)) (+ res), input channels [0, c0) from x0 and [c0, cin) from x1;
+// wf (the forward layout, or null) selects the matrix-core kernel where the layer allows it.
 hipError_t conv_fwd(int ks, const float* x0, int c0, const float* x1, int cin, const __hip_bfloat16* w,
-                    const float* b, float* out, int cout, int n, int relu, const float* res, hipStream_t s);
-// Input gradient of a conv layer; g masked by (y > 0) unless y is null; channels [0, c0) into gx0.
-hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const __hip_bfloat16* w, float* gx0,
-                         int c0, float* gx1, int cin, int n, hipStream_t s);
-// Weight and bias gradients (fixed-order chunk partials pw / pb, then their sums into gw / gb).
+                    const unsigned short* wf, const float* b, float* out, int cout, int n, int relu,
+                    const float* res, hipStream_t s);
+// Input gradient of a conv layer; g masked by (y > 0) unless y is null; channels [0, c0) into
+// gx0; wd (the input-gradient layout, or null) selects the matrix-core kernel.
+hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const __hip_bfloat16* w,
+                         const unsigned short* wd, float* gx0, int c0, float* gx1, int cin, int n, hipStream_t s);
+// Weight and bias gradients: fixed-order chunk partials pw / pb, slice sums q, then gw / gb.
 hipError_t conv_bwd_w(int ks, const float* x0, int c0, const float* x1, int cin, const float* g, const float* y,
-                      int cout, int n, float* pw, float* pb, float* gw, float* gb, hipStream_t s);
-int weight_grad_chunks(int n);
+                      int cout, int n, float* pw, float* pb, float* q, float* gw, float* gb, hipStream_t s);
+// Workspace (floats) conv_bwd_w needs for a layer.
+void wgrad_workspace(int ks, int cin, int cout, int n, size_t& pw_floats, size_t& pb_floats, size_t& q_floats);
 hipError_t pool2(const float* x, float* y, int c, int n, hipStream_t s);
 hipError_t up2(const float* x, float* y, int c, int n, hipStream_t s);
 hipError_t up2_bwd(const float* g, float* gx, int c, int n, hipStream_t s);

@@ -17,6 +17,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "unet_internal.hpp"
@@ -272,38 +273,21 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ x0
   if (ci0 == 0 && ci_l == 0 && co < cout) pb[size_t(blockIdx.x) * cout + co] = accb;
 }
 
-// grad[w] = sum over chunks (in order) of pw; grad[b] likewise (layer's slice of the gradient vector).
-__global__ void k_reduce_chunks(const float* __restrict__ pw, const float* __restrict__ pb, int chunks, int nw,
-                                int nb, float* __restrict__ gw, float* __restrict__ gb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nw) {
-    float s = 0.0f;
-    for (int k = 0; k < chunks; ++k) s += pw[size_t(k) * nw + i];
-    gw[i] = s;
-  } else if (i < nw + nb) {
-    const int j = i - nw;
-    float s = 0.0f;
-    for (int k = 0; k < chunks; ++k) s += pb[size_t(k) * nb + j];
-    gb[j] = s;
-  }
-}
-
 // ------------------------------------------------------------------ matrix-core convolutions
-// The 3x3x3 convolutions with 16-multiple channel counts run on the matrix cores as
-// implicit GEMMs with v_mfma_f32_16x16x16_bf16 (16 voxels x 16 channels x 16 channels per
-// instruction; lane l holds A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16] and
-// D[4(l/16)+i][l%16]).  Weights are BF16 values already; an FP32 activation or gradient
-// is split into BF16 hi + lo (v = hi + lo + e, |e| <= 2^-18 |v|) and both halves are
-// multiplied, so the result keeps FP32-level accuracy: two instructions per product for
-// the forward and input-gradient passes, three (hi*hi + hi*lo + lo*hi) for the weight
-// gradient, whose operands are both FP32.  Tiles: 8 x 8 x 4 output voxels per workgroup,
-// one z-plane (four 16-voxel blocks) per wave, input channels in chunks of 16 staged in
-// LDS as [voxel][channel] with their halo.
+// The 3x3x3 convolutions run on the matrix cores as implicit GEMMs with
+// v_mfma_f32_16x16x16_bf16 (a 16 x 16 x 16 product per instruction; lane l holds
+// A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16] and D[4(l/16)+i][l%16]).  Weights are BF16
+// values already; an FP32 activation or gradient v is split into BF16 hi + lo
+// (v = hi + lo + e, |e| <= 2^-18 |v|) and both halves are multiplied, so the products keep
+// FP32-level accuracy: two instructions per product in the forward and input-gradient
+// passes, three (hi*hi + hi*lo + lo*hi) in the weight gradient, whose operands are both
+// FP32.
+//
+// LDS layouts follow one rule: a 64-bit LDS read is served sixteen lanes at a time, so the
+// sixteen lanes of a group (the M or N index of the product) read 128 contiguous bytes;
+// staging writes from lanes that walk along x use strides of 2 (mod 32) dwords.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int MHV = 600;   // halo voxels of an 8 x 8 x 4 tile (10 x 10 x 6)
-constexpr int MVS = 20;    // LDS stride of a halo voxel (16 channels + 4 pad shorts: 40 bytes)
 
 __device__ __forceinline__ unsigned short bf_bits(float v) {
   const __hip_bfloat16 h = __float2bfloat16(v);
@@ -311,54 +295,190 @@ __device__ __forceinline__ unsigned short bf_bits(float v) {
 }
 __device__ __forceinline__ float bits_bf(unsigned short u) { return __uint_as_float(unsigned(u) << 16); }
 
-__device__ __forceinline__ void split_bf16(float v, unsigned short& hi, unsigned short& lo) {
+__device__ __forceinline__ void split_bf16(float v, unsigned& hi, unsigned& lo) {
   hi = bf_bits(v);
-  lo = bf_bits(v - bits_bf(hi));
+  lo = bf_bits(v - bits_bf(static_cast<unsigned short>(hi)));
+}
+
+// hi / lo halves of four values, packed as four BF16 each
+__device__ __forceinline__ void split4(const float* v, uint2& hi, uint2& lo) {
+  unsigned h[4], l[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) split_bf16(v[j], h[j], l[j]);
+  hi = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+  lo = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
 }
 
 __device__ __forceinline__ f32x4 mfma16(const bf16x4 a, const bf16x4 b, const f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// Stage 16 channels [ch0, ch0 + 16) of a (two-source) input around the tile, split hi / lo;
-// with mask (non-null) the value is multiplied by (mask > 0) first.
-__device__ __forceinline__ void stage_split(unsigned short* xh, unsigned short* xl, const float* x0, int c0,
-                                            const float* x1, int cin, int ch0, const float* mask, int n,
-                                            int x0t, int y0t, int z0t, size_t vol) {
-  for (int idx = threadIdx.x; idx < 16 * MHV; idx += 256) {
-    const int c = idx / MHV, hv = idx % MHV;
-    const int hz = hv / 100, hy = (hv / 10) % 10, hx = hv % 10;
-    const int gz = z0t + hz - 1, gy = y0t + hy - 1, gx = x0t + hx - 1;
-    float v = 0.0f;
-    if (ch0 + c < cin && unsigned(gz) < unsigned(n) && unsigned(gy) < unsigned(n) && unsigned(gx) < unsigned(n)) {
-      const size_t off = (size_t(gz) * n + gy) * n + gx;
-      v = chan(x0, c0, x1, ch0 + c, vol)[off];
-      if (mask && !(mask[size_t(ch0 + c) * vol + off] > 0.0f)) v = 0.0f;
+__device__ __forceinline__ bf16x4 lds4(const unsigned short* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
+// ---- forward and input gradient: output tiles of 16 x 4 x 4 voxels (x, y, z), halo 18 x 6 x 6;
+// wave w computes z-plane w, its four 16-voxel blocks being the four x-rows.  These use
+// v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16]) with
+// the hi and lo halves of 16 input channels packed into K = 32: A = [hi c0..15, lo c0..15],
+// B = [w c0..15, w c0..15], so one instruction forms sum_c (hi + lo) w.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma32(const bf16x8 a, const bf16x8 b, const f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 lds8(const unsigned short* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+constexpr int FHX = 18, FHY = 6, FHV = 18 * 6 * 6;
+
+__host__ __device__ __forceinline__ int ftiles(int n) { return ((n + 15) / 16) * ((n + 3) / 4) * ((n + 3) / 4); }
+
+__device__ __forceinline__ void ftile_origin(int tile, int n, int& x0t, int& y0t, int& z0t) {
+  const int ntx = (n + 15) / 16, nty = (n + 3) / 4;
+  x0t = (tile % ntx) * 16;
+  y0t = ((tile / ntx) % nty) * 4;
+  z0t = (tile / (ntx * nty)) * 4;
+}
+
+__device__ __forceinline__ uint4 pack8(const unsigned* h) {
+  return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
+// Stage 16 channels [ch0, ch0 + 16) of a two-source input around the tile into LDS as
+// [4 parts][648 halo voxels][8] BF16: part 0 / 1 = hi of channels 0-7 / 8-15, part 2 / 3 =
+// lo of the same; with MASK a value is zeroed where mask <= 0.  Work item it = 648 h + hv
+// covers channels 8 h .. 8 h + 7 of halo voxel hv.  Loads are unconditional (an
+// out-of-range element reads voxel 0 of its channel and is zeroed) and issued in batches.
+template <bool MASK>
+__device__ __forceinline__ void stage_vox16(unsigned short* xs, const float* x0, int c0, const float* x1, int ch0,
+                                            const float* mask, int n, int x0t, int y0t, int z0t, size_t vol) {
+  constexpr int ITEMS = 2 * FHV, PER = (ITEMS + 255) / 256, BATCH = MASK ? 2 : 3;
+#pragma unroll
+  for (int k0 = 0; k0 < PER; k0 += BATCH) {
+    float v[BATCH][8], mk[BATCH][8];
+    bool in[BATCH];
+#pragma unroll
+    for (int kk = 0; kk < BATCH; ++kk) {
+      const int it = threadIdx.x + 256 * (k0 + kk);
+      const int h = min(it / FHV, 1), hv = it % FHV;
+      const int hz = hv / (FHX * FHY), hy = (hv / FHX) % FHY, hx = hv % FHX;
+      const int gz = z0t + hz - 1, gy = y0t + hy - 1, gx = x0t + hx - 1;
+      in[kk] = k0 + kk < PER && it < ITEMS && unsigned(gz) < unsigned(n) && unsigned(gy) < unsigned(n) &&
+               unsigned(gx) < unsigned(n);
+      const size_t off = in[kk] ? (size_t(gz) * n + gy) * n + gx : 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = ch0 + 8 * h + j;
+        v[kk][j] = chan(x0, c0, x1, c, vol)[off];
+        if (MASK) mk[kk][j] = mask[size_t(c) * vol + off];
+      }
     }
-    unsigned short hi, lo;
-    split_bf16(v, hi, lo);
-    xh[hv * MVS + c] = hi;
-    xl[hv * MVS + c] = lo;
+#pragma unroll
+    for (int kk = 0; kk < BATCH; ++kk) {
+      const int it = threadIdx.x + 256 * (k0 + kk);
+      unsigned hi[8], lo[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        split_bf16(in[kk] && (!MASK || mk[kk][j] > 0.0f) ? v[kk][j] : 0.0f, hi[j], lo[j]);
+      if (k0 + kk < PER && it < ITEMS) {
+        const int h = it / FHV, hv = it % FHV;
+        reinterpret_cast<uint4*>(xs)[h * FHV + hv] = pack8(hi);
+        reinterpret_cast<uint4*>(xs)[(2 + h) * FHV + hv] = pack8(lo);
+      }
+    }
   }
 }
 
-// Forward: out[co] = act(b + conv(in)), cout = 16 NB, cin a multiple of 16.
+// contiguous copy of `shorts` BF16 values (a multiple of 8) from global memory into LDS, in
+// rounds of four unconditional 16-byte loads per thread
+__device__ __forceinline__ void copy_weights(unsigned short* dst, const unsigned short* src, int shorts) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const int n16 = shorts / 8;
+  for (int base = 0; base < n16; base += 1024) {
+    uint4 r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = s[min(base + int(threadIdx.x) + 256 * j, n16 - 1)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = base + int(threadIdx.x) + 256 * j;
+      if (i < n16) d[i] = r[j];
+    }
+  }
+}
+
+// The 27-tap product of one wave: its z-plane of the tile times NB 16-channel blocks of the
+// staged weights ws[tap][2][NB*16][8].  For each (dz, dx) the six halo rows the wave needs
+// are read once and serve the three dy taps.
+template <int NB>
+__device__ __forceinline__ void taps_product(const unsigned short* xs, const unsigned short* ws, int wave, int m,
+                                             int kg, f32x4 (&acc)[4][NB]) {
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      bf16x8 a[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) a[r] = lds8(&xs[(kg * FHV + ((wave + dz) * FHY + r) * FHX + m + dx) * 8]);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int tap = (dz * 3 + dy) * 3 + dx;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8 bw = lds8(&ws[((tap * 2 + (kg & 1)) * (NB * 16) + 16 * nb + m) * 8]);
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) acc[mb][nb] = mfma32(a[mb + dy], bw, acc[mb][nb]);
+        }
+      }
+    }
+}
+
+// Write a finished tile through LDS so that global stores are whole 16-byte x-runs: the
+// accumulators go to o[c][z][y][x] (channel stride OS floats), then thread groups store
+// float4s of each channel's rows.  dst(c) gives channel c's output volume.
+constexpr int OS = 260;   // 256 + 4: the float4 writes of eight lanes hit distinct banks
+
+template <int NB, class Dst>
+__device__ __forceinline__ void store_tile(const f32x4 (&acc)[4][NB], float* o, int wave, int m, int kg, int n,
+                                           int x0t, int y0t, int z0t, Dst dst) {
+  __syncthreads();
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      *reinterpret_cast<f32x4*>(&o[(16 * nb + m) * OS + wave * 64 + mb * 16 + 4 * kg]) = acc[mb][nb];
+  __syncthreads();
+  const size_t vol = size_t(n) * n * n;
+  (void)vol;
+  for (int f = threadIdx.x; f < NB * 16 * 64; f += 256) {
+    const int c = f >> 6, z = (f >> 4) & 3, yy = (f >> 2) & 3, xq = f & 3;
+    const int gz = z0t + z, gy = y0t + yy, gx = x0t + 4 * xq;
+    if (gz >= n || gy >= n || gx >= n) continue;
+    const f32x4 v = *reinterpret_cast<const f32x4*>(&o[c * OS + z * 64 + yy * 16 + 4 * xq]);
+    float* d = dst(c) + (size_t(gz) * n + gy) * n + gx;
+    if ((n & 3) == 0) {
+      *reinterpret_cast<f32x4*>(d) = v;
+    } else {
+      for (int i = 0; i < 4 && gx + i < n; ++i) d[i] = v[i];
+    }
+  }
+}
+
+// Forward: out[co] = act(b + conv(in)) for cout = 16 NB, cin a multiple of 16; wf holds the
+// layer's weights as [cin/16][27][2][cout][8] BF16 (input channel 16 chunk + 8 half + i).
 template <int NB>
 __global__ __launch_bounds__(256) void k_conv_fwd_mfma(const float* __restrict__ x0, int c0,
                                                        const float* __restrict__ x1, int cin,
-                                                       const __hip_bfloat16* __restrict__ w,
+                                                       const unsigned short* __restrict__ wf,
                                                        const float* __restrict__ b, float* __restrict__ out, int n,
                                                        int relu) {
-  __shared__ __attribute__((aligned(16))) unsigned short xh[MHV * MVS];
-  __shared__ __attribute__((aligned(16))) unsigned short xl[MHV * MVS];
-  __shared__ __attribute__((aligned(16))) unsigned short ws[27 * NB * 16 * 16];
+  constexpr int XS = 4 * FHV * 8, WS = 27 * NB * 16 * 16;   // shorts
+  __shared__ __attribute__((aligned(16))) unsigned short smem[XS + WS];
+  unsigned short* xs = smem;
+  unsigned short* ws = smem + XS;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int m = lane & 15, kg = lane >> 4;
-  const int ntx = (n + 7) / 8;
-  const int tile = blockIdx.x;
-  const int x0t = (tile % ntx) * 8, y0t = ((tile / ntx) % ntx) * 8, z0t = (tile / (ntx * ntx)) * 4;
+  int x0t, y0t, z0t;
+  ftile_origin(blockIdx.x, n, x0t, y0t, z0t);
   const size_t vol = size_t(n) * n * n;
-  const unsigned short* wb = reinterpret_cast<const unsigned short*>(w);
   f32x4 acc[4][NB];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -366,68 +486,44 @@ __global__ __launch_bounds__(256) void k_conv_fwd_mfma(const float* __restrict__
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int ci0 = 0; ci0 < cin; ci0 += 16) {
     __syncthreads();
-    stage_split(xh, xl, x0, c0, x1, cin, ci0, nullptr, n, x0t, y0t, z0t, vol);
-    for (int idx = t; idx < 27 * NB * 16 * 16; idx += 256) {
-      const int c = idx % 16, co = (idx / 16) % (NB * 16), tap = idx / (16 * NB * 16);
-      ws[idx] = wb[(size_t(co) * cin + ci0 + c) * 27 + tap];
-    }
+    stage_vox16<false>(xs, x0, c0, x1, ci0, nullptr, n, x0t, y0t, z0t, vol);
+    copy_weights(ws, wf + size_t(ci0 / 16) * (27 * NB * 256), 27 * NB * 256);
     __syncthreads();
-    for (int tap = 0; tap < 27; ++tap) {
-      const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-      bf16x4 ah[4], al[4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const int hv = ((wave + dz) * 10 + (2 * mb + (m >> 3) + dy)) * 10 + (m & 7) + dx;
-        ah[mb] = *reinterpret_cast<const bf16x4*>(&xh[hv * MVS + 4 * kg]);
-        al[mb] = *reinterpret_cast<const bf16x4*>(&xl[hv * MVS + 4 * kg]);
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const bf16x4 bw = *reinterpret_cast<const bf16x4*>(&ws[((tap * NB + nb) * 16 + m) * 16 + 4 * kg]);
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          acc[mb][nb] = mfma16(ah[mb], bw, acc[mb][nb]);
-          acc[mb][nb] = mfma16(al[mb], bw, acc[mb][nb]);
-        }
-      }
-    }
+    taps_product<NB>(xs, ws, wave, m, kg, acc);
   }
-  const int gz = z0t + wave;
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int nb = 0; nb < NB; ++nb) {
+    const float bias = b[16 * nb + m];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int mm = 4 * kg + i;
-      const int gy = y0t + 2 * mb + (mm >> 3), gx = x0t + (mm & 7);
-      if (gz >= n || gy >= n || gx >= n) continue;
-      const size_t v = (size_t(gz) * n + gy) * n + gx;
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int co = 16 * nb + m;
-        float o = acc[mb][nb][i] + b[co];
-        if (relu) o = fmaxf(o, 0.0f);
-        out[size_t(co) * vol + v] = o;
+      for (int i = 0; i < 4; ++i) {
+        const float o = acc[mb][nb][i] + bias;
+        acc[mb][nb][i] = relu ? fmaxf(o, 0.0f) : o;
       }
-    }
+  }
+  store_tile<NB>(acc, reinterpret_cast<float*>(smem), wave, m, kg, n, x0t, y0t, z0t,
+                 [=](int c) { return out + size_t(c) * vol; });
 }
 
-// Input gradient: gx[ci] = sum_co sum_t w[co][ci][t] gm[co][r + 1 - t], gm = g (y > 0);
-// cin = 16 NBI output channels (split over gx0 / gx1 at c0), cout a multiple of 16.
+// Input gradient: gx[ci] = sum_co sum_t w[co][ci][t] gm[co][r + 1 - t], gm = g (y > 0), for
+// cin = 16 NBI (channels [0, c0) into gx0, the rest into gx1) and cout a multiple of 16; wd
+// holds the weights as [cout/16][27][2][cin][8] BF16 with the taps reversed, so that the
+// product is the same cross-correlation as the forward one.
 template <int NBI>
 __global__ __launch_bounds__(256) void k_conv_bwd_data_mfma(const float* __restrict__ g, const float* __restrict__ y,
-                                                            int cout, const __hip_bfloat16* __restrict__ w,
+                                                            int cout, const unsigned short* __restrict__ wd,
                                                             float* __restrict__ gx0, int c0,
-                                                            float* __restrict__ gx1, int cin, int n) {
-  __shared__ __attribute__((aligned(16))) unsigned short gh[MHV * MVS];
-  __shared__ __attribute__((aligned(16))) unsigned short gl[MHV * MVS];
-  __shared__ __attribute__((aligned(16))) unsigned short ws[27 * NBI * 16 * 16];
+                                                            float* __restrict__ gx1, int n) {
+  constexpr int XS = 4 * FHV * 8, WS = 27 * NBI * 16 * 16;   // shorts
+  __shared__ __attribute__((aligned(16))) unsigned short smem[XS + WS];
+  unsigned short* gs = smem;
+  unsigned short* ws = smem + XS;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int m = lane & 15, kg = lane >> 4;
-  const int ntx = (n + 7) / 8;
-  const int tile = blockIdx.x;
-  const int x0t = (tile % ntx) * 8, y0t = ((tile / ntx) % ntx) * 8, z0t = (tile / (ntx * ntx)) * 4;
+  int x0t, y0t, z0t;
+  ftile_origin(blockIdx.x, n, x0t, y0t, z0t);
   const size_t vol = size_t(n) * n * n;
-  const unsigned short* wb = reinterpret_cast<const unsigned short*>(w);
   f32x4 acc[4][NBI];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -435,170 +531,402 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_mfma(const float* __restr
     for (int nb = 0; nb < NBI; ++nb) acc[mb][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int o0 = 0; o0 < cout; o0 += 16) {
     __syncthreads();
-    stage_split(gh, gl, g, cout, nullptr, cout, o0, y, n, x0t, y0t, z0t, vol);
-    // ws[tap'][ci][c] = w[o0 + c][ci][26 - tap'] (flipped taps)
-    for (int idx = t; idx < 27 * NBI * 16 * 16; idx += 256) {
-      const int c = idx % 16, ci = (idx / 16) % (NBI * 16), tp = idx / (16 * NBI * 16);
-      ws[idx] = wb[(size_t(o0 + c) * cin + ci) * 27 + (26 - tp)];
-    }
+    stage_vox16<true>(gs, g, cout, nullptr, o0, y, n, x0t, y0t, z0t, vol);
+    copy_weights(ws, wd + size_t(o0 / 16) * (27 * NBI * 256), 27 * NBI * 256);
     __syncthreads();
-    for (int tap = 0; tap < 27; ++tap) {
-      const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-      bf16x4 ah[4], al[4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const int hv = ((wave + dz) * 10 + (2 * mb + (m >> 3) + dy)) * 10 + (m & 7) + dx;
-        ah[mb] = *reinterpret_cast<const bf16x4*>(&gh[hv * MVS + 4 * kg]);
-        al[mb] = *reinterpret_cast<const bf16x4*>(&gl[hv * MVS + 4 * kg]);
-      }
-#pragma unroll
-      for (int nb = 0; nb < NBI; ++nb) {
-        const bf16x4 bw = *reinterpret_cast<const bf16x4*>(&ws[((tap * NBI + nb) * 16 + m) * 16 + 4 * kg]);
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          acc[mb][nb] = mfma16(ah[mb], bw, acc[mb][nb]);
-          acc[mb][nb] = mfma16(al[mb], bw, acc[mb][nb]);
-        }
-      }
-    }
+    taps_product<NBI>(gs, ws, wave, m, kg, acc);
   }
-  const int gz = z0t + wave;
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int mm = 4 * kg + i;
-      const int gy = y0t + 2 * mb + (mm >> 3), gx = x0t + (mm & 7);
-      if (gz >= n || gy >= n || gx >= n) continue;
-      const size_t v = (size_t(gz) * n + gy) * n + gx;
-#pragma unroll
-      for (int nb = 0; nb < NBI; ++nb) {
-        const int ci = 16 * nb + m;
-        float* dst = ci < c0 ? gx0 + size_t(ci) * vol : gx1 + size_t(ci - c0) * vol;
-        dst[v] = acc[mb][nb][i];
-      }
-    }
+  store_tile<NBI>(acc, reinterpret_cast<float*>(smem), wave, m, kg, n, x0t, y0t, z0t,
+                  [=](int c) { return c < c0 ? gx0 + size_t(c) * vol : gx1 + size_t(c - c0) * vol; });
 }
 
-// Weight gradient partials: pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1] over a
-// chunk of 8x8x4 tiles.  Workgroup = (chunk, 2x2 block of (co, ci) 16-blocks); wave = one
-// (co, ci) block with 27 accumulators; a 16-voxel K step is one z-plane half-tile row pair.
+// ---- weight gradient: tiles of 8 x 8 x 4 voxels, halo 10 x 10 x 6.  The reduction runs over
+// voxels; the input's halo z range is kept as three 4-deep windows (window w holding halo
+// z = w .. w + 3), so that a tap (dz, dy, dx) reads aligned groups of four z.  Layouts of the
+// single-input-channel kernel (16 x 16 x 16 products, K step = 4 columns x 4 z):
+//   A (masked output gradient): [64 columns][16 co][4 z], column stride WA_S shorts;
+//   B (layer input): [100 halo columns][3 windows][4].
+constexpr int WA_S = 68;            // 64 + 4: staging writes along x are conflict-free
+constexpr int WA_PER = 4;           // A items (co, column) per thread: 16 * 64 / 256
+constexpr int WB_PER = 7;           // B items (ci, halo column) per thread: ceil(16 * 100 / 256)
+
+__host__ __device__ __forceinline__ int wtiles(int n) { return ((n + 7) / 8) * ((n + 7) / 8) * ((n + 3) / 4); }
+
+__device__ __forceinline__ void wtile_origin(int tile, int n, int& x0t, int& y0t, int& z0t) {
+  const int ntx = (n + 7) / 8;
+  x0t = (tile % ntx) * 8;
+  y0t = ((tile / ntx) % ntx) * 8;
+  z0t = (tile / (ntx * ntx)) * 4;
+}
+
+struct WTileRegs {
+  float g[WA_PER][4], y[WA_PER][4];
+  float x[WB_PER][6];
+  unsigned va;                 // validity of g (bit 4 k + z)
+  unsigned long long vb;       // validity of x (bit 6 k + hz)
+};
+
+// Load (into registers) the tile's output-gradient block of channels co0 .. co0 + 15 with
+// the layer output y (for the ReLU mask) and its input channels ci0 .. ci0 + nci - 1 (nci =
+// 16, or 1 for the single-channel first layer).  Loads are unconditional (out-of-range
+// elements read a valid address) and their values are not touched here, so that the loads
+// of the next tile stay in flight while the current one is multiplied; validity is kept as
+// bit masks and applied when the tile is stored.
+__device__ __forceinline__ void wtile_load(WTileRegs& r, const float* x0, int c0, const float* x1, const float* g,
+                                           const float* y, int co0, int ci0, int nci, int n, int x0t, int y0t,
+                                           int z0t, size_t vol) {
+  r.va = 0;
+  r.vb = 0;
+#pragma unroll
+  for (int k = 0; k < WA_PER; ++k) {
+    const int it = threadIdx.x + 256 * k;
+    const int co = co0 + (it >> 6), col = it & 63;
+    const int gy = y0t + (col >> 3), gx = x0t + (col & 7);
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      const int gz = z0t + z;
+      const bool in = gz < n && gy < n && gx < n;
+      const size_t a = size_t(co) * vol + (in ? (size_t(gz) * n + gy) * n + gx : 0);
+      r.g[k][z] = g[a];
+      r.y[k][z] = y[a];
+      r.va |= unsigned(in) << (4 * k + z);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < WB_PER; ++k) {
+    const int it = threadIdx.x + 256 * k;
+    const int c = it / 100, cp = it % 100;
+    const int gy = y0t + cp / 10 - 1, gx = x0t + cp % 10 - 1;
+    const bool inc = c < nci && unsigned(gy) < unsigned(n) && unsigned(gx) < unsigned(n);
+    const float* src = chan(x0, c0, x1, ci0 + min(c, nci - 1), vol);
+#pragma unroll
+    for (int hz = 0; hz < 6; ++hz) {
+      const int gz = z0t + hz - 1;
+      const bool in = inc && unsigned(gz) < unsigned(n);
+      r.x[k][hz] = src[in ? (size_t(gz) * n + gy) * n + gx : 0];
+      r.vb |= static_cast<unsigned long long>(in) << (6 * k + hz);
+    }
+  }
+}
+
+__device__ __forceinline__ float wtile_g(const WTileRegs& r, int k, int z) {
+  return ((r.va >> (4 * k + z)) & 1u) && r.y[k][z] > 0.0f ? r.g[k][z] : 0.0f;
+}
+__device__ __forceinline__ float wtile_x(const WTileRegs& r, int k, int hz) {
+  return ((r.vb >> (6 * k + hz)) & 1ull) ? r.x[k][hz] : 0.0f;
+}
+
+// Split the loaded tile into the LDS layouts (B with CI channels per window and halo-column
+// stride BS); adds the masked gradient to bsum (bias).
+template <int CI, int BS>
+__device__ __forceinline__ void wtile_store(const WTileRegs& r, unsigned short* ah, unsigned short* al,
+                                            unsigned short* bh, unsigned short* bl, float (&bsum)[WA_PER]) {
+#pragma unroll
+  for (int k = 0; k < WA_PER; ++k) {
+    const int it = threadIdx.x + 256 * k;
+    const int co = it >> 6, col = it & 63;
+    float v[4];
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      v[z] = wtile_g(r, k, z);
+      bsum[k] += v[z];
+    }
+    uint2 hi, lo;
+    split4(v, hi, lo);
+    *reinterpret_cast<uint2*>(&ah[col * WA_S + co * 4]) = hi;
+    *reinterpret_cast<uint2*>(&al[col * WA_S + co * 4]) = lo;
+  }
+#pragma unroll
+  for (int k = 0; k < WB_PER; ++k) {
+    const int it = threadIdx.x + 256 * k;
+    const int c = it / 100, cp = it % 100;
+    if (c >= CI) continue;
+    unsigned h[6], l[6];
+#pragma unroll
+    for (int hz = 0; hz < 6; ++hz) split_bf16(wtile_x(r, k, hz), h[hz], l[hz]);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const int o = cp * BS + (w * CI + c) * 4;
+      *reinterpret_cast<uint2*>(&bh[o]) = make_uint2(h[w] | (h[w + 1] << 16), h[w + 2] | (h[w + 3] << 16));
+      *reinterpret_cast<uint2*>(&bl[o]) = make_uint2(l[w] | (l[w + 1] << 16), l[w + 2] | (l[w + 3] << 16));
+    }
+  }
+}
+
+// Fixed-order bias sum of the workgroup: thread t holds co = t / 64 + 4 k.
+__device__ __forceinline__ void wtile_bias(const float (&bsum)[WA_PER], float* red, float* dst) {
+#pragma unroll
+  for (int k = 0; k < WA_PER; ++k) red[k * 256 + threadIdx.x] = bsum[k];
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int co = threadIdx.x;
+    const float* p = red + (co >> 2) * 256 + (co & 3) * 64;
+    float s = 0.0f;
+    for (int j = 0; j < 64; ++j) s += p[j];
+    dst[co] = s;
+  }
+}
+
+// Layouts of the 16-channel weight-gradient kernel, which uses v_mfma_f32_16x16x32_bf16 with
+// K = 32 voxels (one y-row of the tile plane x 4 z; lane group q holds columns 2q, 2q + 1):
+//   A (masked output gradient), hi and lo: [32 column pairs][16 co][2 columns x 4 z], pair
+//     stride PA_S shorts;
+//   B (layer input): [100 halo columns][3 windows][16 ci][hi 4 z | lo 4 z], halo-column
+//     stride PB_S shorts.
+constexpr int PA_S = 136;           // 128 + 8: staging writes along x are conflict-free
+constexpr int PB_S = 392;           // 3 * 16 * 8 + 8, likewise
+
+__device__ __forceinline__ void wtile_store32(const WTileRegs& r, unsigned short* ah, unsigned short* al,
+                                              unsigned short* bx, float (&bsum)[WA_PER]) {
+#pragma unroll
+  for (int k = 0; k < WA_PER; ++k) {
+    const int it = threadIdx.x + 256 * k;
+    const int co = it >> 6, col = it & 63;
+    float v[4];
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      v[z] = wtile_g(r, k, z);
+      bsum[k] += v[z];
+    }
+    uint2 hi, lo;
+    split4(v, hi, lo);
+    const int o = (col >> 1) * PA_S + co * 8 + (col & 1) * 4;
+    *reinterpret_cast<uint2*>(&ah[o]) = hi;
+    *reinterpret_cast<uint2*>(&al[o]) = lo;
+  }
+#pragma unroll
+  for (int k = 0; k < WB_PER; ++k) {
+    const int it = threadIdx.x + 256 * k;
+    const int c = it / 100, cp = it % 100;
+    if (c >= 16) continue;
+    unsigned h[6], l[6];
+#pragma unroll
+    for (int hz = 0; hz < 6; ++hz) split_bf16(wtile_x(r, k, hz), h[hz], l[hz]);
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+      *reinterpret_cast<uint4*>(&bx[cp * PB_S + (w * 16 + c) * 8]) =
+          make_uint4(h[w] | (h[w + 1] << 16), h[w + 2] | (h[w + 3] << 16), l[w] | (l[w + 1] << 16),
+                     l[w + 2] | (l[w + 3] << 16));
+  }
+}
+
+// Weight-gradient partials of a 16 x 16 (co, ci) block over a chunk of tiles:
+// pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1]; wave w owns taps w, w + 4, ...
+// Each 32-voxel step takes three products (hi hi, hi lo, lo hi).  The workgroup with ci
+// block 0 also writes the bias partial pb[chunk][co].  The next tile's loads are in flight
+// while the current one is multiplied.
 __global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(const float* __restrict__ x0, int c0,
                                                          const float* __restrict__ x1, int cin,
                                                          const float* __restrict__ g, const float* __restrict__ y,
                                                          int cout, int n, int tiles_per_chunk,
-                                                         float* __restrict__ pw) {
-  constexpr int TV = 256;                                // voxels of a tile
-  __shared__ __attribute__((aligned(16))) unsigned short ah_s[2][16][TV];
-  __shared__ __attribute__((aligned(16))) unsigned short al_s[2][16][TV];
-  __shared__ unsigned short bh_s[2][16][MHV];
-  __shared__ unsigned short bl_s[2][16][MHV];
+                                                         float* __restrict__ pw, float* __restrict__ pb) {
+  __shared__ __attribute__((aligned(16))) unsigned short ah[32 * PA_S];
+  __shared__ __attribute__((aligned(16))) unsigned short al[32 * PA_S];
+  __shared__ __attribute__((aligned(16))) unsigned short bx[100 * PB_S];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int m = lane & 15, kg = lane >> 4;
-  const int ncb = cout / 16, nib = cin / 16;
-  const int nqc = (ncb + 1) / 2;
-  const int cb0 = 2 * (blockIdx.y % nqc), ib0 = 2 * (blockIdx.y / nqc);
-  const int cbl = wave >> 1, ibl = wave & 1;             // this wave's block within the quad
-  const bool active = cb0 + cbl < ncb && ib0 + ibl < nib;
-  const int ntx = (n + 7) / 8, ntz = (n + 3) / 4;
-  const int ntiles = ntx * ntx * ntz;
+  const int nco = cout / 16;
+  const int cb = blockIdx.y % nco, ib = blockIdx.y / nco;
+  const int ntiles = wtiles(n);
   const size_t vol = size_t(n) * n * n;
-  f32x4 acc[27];
+  // this wave's taps and their offsets within B
+  int toff[7];
 #pragma unroll
-  for (int k = 0; k < 27; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  const int tile_end = min(ntiles, (int(blockIdx.x) + 1) * tiles_per_chunk);
-  for (int tile = blockIdx.x * tiles_per_chunk; tile < tile_end; ++tile) {
-    const int x0t = (tile % ntx) * 8, y0t = ((tile / ntx) % ntx) * 8, z0t = (tile / (ntx * ntx)) * 4;
+  for (int j = 0; j < 7; ++j) {
+    const int tap = min(wave + 4 * j, 26);
+    toff[j] = (((tap / 3) % 3) * 10 + tap % 3) * PB_S + (tap / 9) * 128;
+  }
+  const int ntap = wave == 3 ? 6 : 7;
+  f32x4 acc[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  float bsum[WA_PER] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int tile0 = blockIdx.x * tiles_per_chunk;
+  const int tile_end = min(ntiles, tile0 + tiles_per_chunk);
+  WTileRegs r;
+  if (tile0 < tile_end) {
+    int x0t, y0t, z0t;
+    wtile_origin(tile0, n, x0t, y0t, z0t);
+    wtile_load(r, x0, c0, x1, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
+  }
+  for (int tile = tile0; tile < tile_end; ++tile) {
     __syncthreads();
-    // masked output gradient of the quad's two co blocks, split, [block][co][voxel]
-    for (int idx = t; idx < 2 * 16 * TV; idx += 256) {
-      const int v = idx % TV, c = (idx / TV) % 16, blk = idx / (16 * TV);
-      const int co = 16 * (cb0 + blk) + c;
-      const int gz = z0t + v / 64, gy = y0t + (v / 8) % 8, gx = x0t + v % 8;
-      float val = 0.0f;
-      if (co < cout && gz < n && gy < n && gx < n) {
-        const size_t a = size_t(co) * vol + (size_t(gz) * n + gy) * n + gx;
-        val = g[a];
-        if (y && !(y[a] > 0.0f)) val = 0.0f;
+    wtile_store32(r, ah, al, bx, bsum);
+    __syncthreads();
+    if (tile + 1 < tile_end) {
+      int x0t, y0t, z0t;
+      wtile_origin(tile + 1, n, x0t, y0t, z0t);
+      wtile_load(r, x0, c0, x1, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
+    }
+#pragma unroll 2
+    for (int row = 0; row < 8; ++row) {
+      const int pr = 4 * row + kg;
+      const bf16x8 a_hi = lds8(&ah[pr * PA_S + m * 8]);
+      const bf16x8 a_lo = lds8(&al[pr * PA_S + m * 8]);
+      const int base = (row * 10 + 2 * kg) * PB_S + m * 8;
+      bf16x8 b_hi[7], b_lo[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        if (j == 6 && ntap == 6) break;
+        const uint4 r0 = *reinterpret_cast<const uint4*>(&bx[base + toff[j]]);
+        const uint4 r1 = *reinterpret_cast<const uint4*>(&bx[base + toff[j] + PB_S]);
+        const uint4 bh4 = make_uint4(r0.x, r0.y, r1.x, r1.y), bl4 = make_uint4(r0.z, r0.w, r1.z, r1.w);
+        b_hi[j] = *reinterpret_cast<const bf16x8*>(&bh4);
+        b_lo[j] = *reinterpret_cast<const bf16x8*>(&bl4);
       }
-      unsigned short hi, lo;
-      split_bf16(val, hi, lo);
-      ah_s[blk][c][v] = hi;
-      al_s[blk][c][v] = lo;
-    }
-    // input of the quad's two ci blocks with the halo, split, [block][ci][halo voxel]
-    for (int idx = t; idx < 2 * 16 * MHV; idx += 256) {
-      const int hv = idx % MHV, c = (idx / MHV) % 16, blk = idx / (16 * MHV);
-      const int ci = 16 * (ib0 + blk) + c;
-      const int hz = hv / 100, hy = (hv / 10) % 10, hx = hv % 10;
-      const int gz = z0t + hz - 1, gy = y0t + hy - 1, gx = x0t + hx - 1;
-      float val = 0.0f;
-      if (ci < cin && unsigned(gz) < unsigned(n) && unsigned(gy) < unsigned(n) && unsigned(gx) < unsigned(n))
-        val = chan(x0, c0, x1, ci, vol)[(size_t(gz) * n + gy) * n + gx];
-      unsigned short hi, lo;
-      split_bf16(val, hi, lo);
-      bh_s[blk][c][hv] = hi;
-      bl_s[blk][c][hv] = lo;
-    }
-    __syncthreads();
-    if (!active) continue;
-    for (int st = 0; st < TV / 16; ++st) {
-      // A: rows co (m), k = voxels 16 st + 4 kg .. + 3
-      const bf16x4 ahi = *reinterpret_cast<const bf16x4*>(&ah_s[cbl][m][16 * st + 4 * kg]);
-      const bf16x4 alo = *reinterpret_cast<const bf16x4*>(&al_s[cbl][m][16 * st + 4 * kg]);
-      // the four voxels of this lane's k group: one x-run of 4 in row (z, y)
-      const int z = st / 4, yy = 2 * (st % 4) + (kg >> 1), xb = 4 * (kg & 1);
 #pragma unroll
-      for (int tap = 0; tap < 27; ++tap) {
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-        const int hv = ((z + dz) * 10 + yy + dy) * 10 + xb + dx;
-        const unsigned short* ph = &bh_s[ibl][m][hv];
-        const unsigned short* pl = &bl_s[ibl][m][hv];
-        const bf16x4 bhi = {short(ph[0]), short(ph[1]), short(ph[2]), short(ph[3])};
-        const bf16x4 blo = {short(pl[0]), short(pl[1]), short(pl[2]), short(pl[3])};
-        acc[tap] = mfma16(ahi, bhi, acc[tap]);
-        acc[tap] = mfma16(ahi, blo, acc[tap]);
-        acc[tap] = mfma16(alo, bhi, acc[tap]);
+      for (int j = 0; j < 7; ++j) {
+        if (j == 6 && ntap == 6) break;
+        acc[j] = mfma32(a_hi, b_hi[j], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        if (j == 6 && ntap == 6) break;
+        acc[j] = mfma32(a_hi, b_lo[j], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        if (j == 6 && ntap == 6) break;
+        acc[j] = mfma32(a_lo, b_hi[j], acc[j]);
       }
     }
   }
-  if (!active) return;
-  const int ci = 16 * (ib0 + ibl) + m;
+  const int ci = 16 * ib + m;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int co = 16 * (cb0 + cbl) + 4 * kg + i;
-    float* dst = pw + (size_t(blockIdx.x) * cout * cin + size_t(co) * cin + ci) * 27;
+  for (int j = 0; j < 7; ++j) {
+    if (j == 6 && ntap == 6) break;
+    const int tap = wave + 4 * j;
 #pragma unroll
-    for (int tap = 0; tap < 27; ++tap) dst[tap] = acc[tap][i];
+    for (int i = 0; i < 4; ++i) {
+      const int co = 16 * cb + 4 * kg + i;
+      pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + tap] = acc[j][i];
+    }
+  }
+  if (ib == 0) {
+    __syncthreads();
+    wtile_bias(bsum, reinterpret_cast<float*>(bx), pb + size_t(blockIdx.x) * cout + 16 * cb);
   }
 }
 
-// Bias-gradient partials pb[chunk][co] = sum over the chunk's tiles of gm[co] (FP32, fixed tree).
-__global__ __launch_bounds__(256) void k_bias_partial(const float* __restrict__ g, const float* __restrict__ y,
-                                                      int cout, int n, int tiles_per_chunk, float* __restrict__ pb) {
-  __shared__ float red[256];
-  const int co = blockIdx.y;
-  const int ntx = (n + 7) / 8, ntz = (n + 3) / 4;
-  const int ntiles = ntx * ntx * ntz;
+// Single-input-channel variant (the first layer): the 27 taps (padded to 32) form the N
+// dimension, B[k][tap] = in[v_k + tap - 1]; wave w takes the K steps st = w, w + 4, ...
+// and the four waves' sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma_c1(const float* __restrict__ x, const float* __restrict__ g,
+                                                            const float* __restrict__ y, int cout, int n,
+                                                            int tiles_per_chunk, float* __restrict__ pw,
+                                                            float* __restrict__ pb) {
+  constexpr int BS1 = 12;
+  __shared__ __attribute__((aligned(16))) unsigned short ah[64 * WA_S];
+  __shared__ __attribute__((aligned(16))) unsigned short al[64 * WA_S];
+  __shared__ __attribute__((aligned(16))) unsigned short bh[100 * BS1];
+  __shared__ __attribute__((aligned(16))) unsigned short bl[100 * BS1];
+  __shared__ float red[4 * 2 * 64 * 4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int m = lane & 15, kg = lane >> 4;
+  const int cb = blockIdx.y;
+  const int ntiles = wtiles(n);
   const size_t vol = size_t(n) * n * n;
-  float s = 0.0f;
-  const int tile_end = min(ntiles, (int(blockIdx.x) + 1) * tiles_per_chunk);
-  for (int tile = blockIdx.x * tiles_per_chunk; tile < tile_end; ++tile) {
-    const int x0t = (tile % ntx) * 8, y0t = ((tile / ntx) % ntx) * 8, z0t = (tile / (ntx * ntx)) * 4;
-    const int v = threadIdx.x;
-    const int gz = z0t + v / 64, gy = y0t + (v / 8) % 8, gx = x0t + v % 8;
-    if (gz < n && gy < n && gx < n) {
-      const size_t a = size_t(co) * vol + (size_t(gz) * n + gy) * n + gx;
-      if (!y || y[a] > 0.0f) s += g[a];
+  int toff[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int tap = min(16 * nb + m, 26);
+    toff[nb] = (((tap / 3) % 3) * 10 + tap % 3) * BS1 + 4 * (tap / 9);
+  }
+  f32x4 acc[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+  float bsum[WA_PER] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int tile0 = blockIdx.x * tiles_per_chunk;
+  const int tile_end = min(ntiles, tile0 + tiles_per_chunk);
+  WTileRegs r;
+  if (tile0 < tile_end) {
+    int x0t, y0t, z0t;
+    wtile_origin(tile0, n, x0t, y0t, z0t);
+    wtile_load(r, x, 1, nullptr, g, y, 16 * cb, 0, 1, n, x0t, y0t, z0t, vol);
+  }
+  for (int tile = tile0; tile < tile_end; ++tile) {
+    __syncthreads();
+    wtile_store<1, BS1>(r, ah, al, bh, bl, bsum);
+    __syncthreads();
+    if (tile + 1 < tile_end) {
+      int x0t, y0t, z0t;
+      wtile_origin(tile + 1, n, x0t, y0t, z0t);
+      wtile_load(r, x, 1, nullptr, g, y, 16 * cb, 0, 1, n, x0t, y0t, z0t, vol);
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int col = 4 * (wave + 4 * s4) + kg;
+      const bf16x4 a_hi = lds4(&ah[col * WA_S + m * 4]);
+      const bf16x4 a_lo = lds4(&al[col * WA_S + m * 4]);
+      const int base = ((col >> 3) * 10 + (col & 7)) * BS1;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const bf16x4 b_hi = lds4(&bh[base + toff[nb]]);
+        const bf16x4 b_lo = lds4(&bl[base + toff[nb]]);
+        acc[nb] = mfma16(a_hi, b_hi, acc[nb]);
+        acc[nb] = mfma16(a_hi, b_lo, acc[nb]);
+        acc[nb] = mfma16(a_lo, b_hi, acc[nb]);
+      }
     }
   }
-  red[threadIdx.x] = s;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[((wave * 2 + nb) * 64 + lane) * 4 + i] = acc[nb][i];
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (int(threadIdx.x) < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int tap = 16 * nb + m;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float s = 0.0f;
+        for (int w = 0; w < 4; ++w) s += red[((w * 2 + nb) * 64 + lane) * 4 + i];
+        if (tap < 27) pw[(size_t(blockIdx.x) * cout + 16 * cb + 4 * kg + i) * 27 + tap] = s;
+      }
+    }
   }
-  if (threadIdx.x == 0) pb[size_t(blockIdx.x) * cout + co] = red[0];
+  __syncthreads();
+  wtile_bias(bsum, reinterpret_cast<float*>(ah), pb + size_t(blockIdx.x) * cout + 16 * cb);
+}
+
+// Two-stage fixed-order sum of the chunk partials: stage 1 sums chunks s, s + S, s + 2S, ...
+// of element i (weights, then biases) into q[s][i]; stage 2 sums q over s in order.
+__global__ void k_reduce_slices(const float* __restrict__ pw, const float* __restrict__ pb, int chunks, int nw,
+                                int nb, int slices, float* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (i >= nw + nb) return;
+  float acc = 0.0f;
+  if (i < nw)
+    for (int k = s; k < chunks; k += slices) acc += pw[size_t(k) * nw + i];
+  else
+    for (int k = s; k < chunks; k += slices) acc += pb[size_t(k) * nb + (i - nw)];
+  q[size_t(s) * (nw + nb) + i] = acc;
+}
+
+__global__ void k_sum_slices(const float* __restrict__ q, int nw, int nb, int slices, float* __restrict__ gw,
+                             float* __restrict__ gb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw + nb) return;
+  float acc = 0.0f;
+  for (int s = 0; s < slices; ++s) acc += q[size_t(s) * (nw + nb) + i];
+  if (i < nw)
+    gw[i] = acc;
+  else
+    gb[i - nw] = acc;
+}
+
+// Weight layouts of a 3x3x3 layer for the matrix-core kernels:
+//   wf[cin/16][27][2][cout][8]:  wf[c][t][h][co][i] = w[co][16 c + 8 h + i][t]  (forward)
+//   wd[cout/16][27][2][cin][8]:  wd[c][t][h][ci][i] = w[16 c + 8 h + i][ci][26 - t]
+//     (input gradient, taps reversed).
+__global__ void k_weight_layout(const __hip_bfloat16* __restrict__ w, int cout, int cin,
+                                unsigned short* __restrict__ wf, unsigned short* __restrict__ wd) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= cout * cin * 27) return;
+  const int tap = idx % 27, ci = (idx / 27) % cin, co = idx / (27 * cin);
+  const unsigned short v = reinterpret_cast<const unsigned short*>(w)[idx];
+  wf[(((size_t(ci / 16) * 27 + tap) * 2 + (ci % 16) / 8) * cout + co) * 8 + ci % 8] = v;
+  wd[(((size_t(co / 16) * 27 + (26 - tap)) * 2 + (co % 16) / 8) * cin + ci) * 8 + co % 8] = v;
 }
 
 // ------------------------------------------------------------------ resampling
@@ -713,19 +1041,28 @@ __global__ void k_round_bf16(const float* __restrict__ th, __hip_bfloat16* __res
 // ------------------------------------------------------------------ launchers
 static unsigned blocks(size_t count) { return unsigned((count + 255) / 256); }
 
-static bool mfma_ok(int ks, int cin, int cout) { return ks == 3 && cin % 16 == 0 && cout % 16 == 0; }
+bool mfma_layer(int ks, int cin, int cout) {
+  return ks == 3 && (cin % 16 == 0 || cin == 1) && cout % 16 == 0 && cout <= 64 && cin <= 96;
+}
+
+hipError_t weight_layout(const __hip_bfloat16* w, int cout, int cin, unsigned short* wf, unsigned short* wd,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_weight_layout, dim3(blocks(size_t(cout) * cin * 27)), dim3(256), 0, s, w, cout, cin, wf, wd);
+  return hipGetLastError();
+}
+
 
 hipError_t conv_fwd(int ks, const float* x0, int c0, const float* x1, int cin, const __hip_bfloat16* w,
-                    const float* b, float* out, int cout, int n, int relu, const float* res, hipStream_t s) {
-  if (mfma_ok(ks, cin, cout) && !res && (cout == 16 || cout == 32 || cout == 64)) {
-    const int ntx = (n + 7) / 8, ntz = (n + 3) / 4;
-    const dim3 grid(unsigned(ntx * ntx * ntz));
-    if (cout == 16)
-      hipLaunchKernelGGL(k_conv_fwd_mfma<1>, grid, dim3(256), 0, s, x0, c0, x1, cin, w, b, out, n, relu);
-    else if (cout == 32)
-      hipLaunchKernelGGL(k_conv_fwd_mfma<2>, grid, dim3(256), 0, s, x0, c0, x1, cin, w, b, out, n, relu);
-    else
-      hipLaunchKernelGGL(k_conv_fwd_mfma<4>, grid, dim3(256), 0, s, x0, c0, x1, cin, w, b, out, n, relu);
+                    const unsigned short* wf, const float* b, float* out, int cout, int n, int relu,
+                    const float* res, hipStream_t s) {
+  if (wf && mfma_layer(ks, cin, cout) && cin % 16 == 0 && !res) {
+    const dim3 grid(unsigned(ftiles(n)));
+    switch (cout / 16) {
+      case 1: hipLaunchKernelGGL(k_conv_fwd_mfma<1>, grid, dim3(256), 0, s, x0, c0, x1, cin, wf, b, out, n, relu); break;
+      case 2: hipLaunchKernelGGL(k_conv_fwd_mfma<2>, grid, dim3(256), 0, s, x0, c0, x1, cin, wf, b, out, n, relu); break;
+      case 4: hipLaunchKernelGGL(k_conv_fwd_mfma<4>, grid, dim3(256), 0, s, x0, c0, x1, cin, wf, b, out, n, relu); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   const int nt = (n + TS - 1) / TS;
@@ -737,17 +1074,16 @@ hipError_t conv_fwd(int ks, const float* x0, int c0, const float* x1, int cin, c
   return hipGetLastError();
 }
 
-hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const __hip_bfloat16* w, float* gx0,
-                         int c0, float* gx1, int cin, int n, hipStream_t s) {
-  if (mfma_ok(ks, cin, cout) && cin <= 96) {
-    const int ntx = (n + 7) / 8, ntz = (n + 3) / 4;
-    const dim3 grid(unsigned(ntx * ntx * ntz));
+hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const __hip_bfloat16* w,
+                         const unsigned short* wd, float* gx0, int c0, float* gx1, int cin, int n, hipStream_t s) {
+  if (wd && y && mfma_layer(ks, cin, cout) && cin % 16 == 0) {   // the matrix-core kernels take the ReLU mask
+    const dim3 grid(unsigned(ftiles(n)));
     switch (cin / 16) {
-      case 1: hipLaunchKernelGGL(k_conv_bwd_data_mfma<1>, grid, dim3(256), 0, s, g, y, cout, w, gx0, c0, gx1, cin, n); break;
-      case 2: hipLaunchKernelGGL(k_conv_bwd_data_mfma<2>, grid, dim3(256), 0, s, g, y, cout, w, gx0, c0, gx1, cin, n); break;
-      case 3: hipLaunchKernelGGL(k_conv_bwd_data_mfma<3>, grid, dim3(256), 0, s, g, y, cout, w, gx0, c0, gx1, cin, n); break;
-      case 4: hipLaunchKernelGGL(k_conv_bwd_data_mfma<4>, grid, dim3(256), 0, s, g, y, cout, w, gx0, c0, gx1, cin, n); break;
-      case 6: hipLaunchKernelGGL(k_conv_bwd_data_mfma<6>, grid, dim3(256), 0, s, g, y, cout, w, gx0, c0, gx1, cin, n); break;
+      case 1: hipLaunchKernelGGL(k_conv_bwd_data_mfma<1>, grid, dim3(256), 0, s, g, y, cout, wd, gx0, c0, gx1, n); break;
+      case 2: hipLaunchKernelGGL(k_conv_bwd_data_mfma<2>, grid, dim3(256), 0, s, g, y, cout, wd, gx0, c0, gx1, n); break;
+      case 3: hipLaunchKernelGGL(k_conv_bwd_data_mfma<3>, grid, dim3(256), 0, s, g, y, cout, wd, gx0, c0, gx1, n); break;
+      case 4: hipLaunchKernelGGL(k_conv_bwd_data_mfma<4>, grid, dim3(256), 0, s, g, y, cout, wd, gx0, c0, gx1, n); break;
+      case 6: hipLaunchKernelGGL(k_conv_bwd_data_mfma<6>, grid, dim3(256), 0, s, g, y, cout, wd, gx0, c0, gx1, n); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -761,42 +1097,63 @@ hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const
   return hipGetLastError();
 }
 
-int weight_grad_chunks(int n) {
-  const int ntx = (n + TS - 1) / TS, ntz = (n + WTZ - 1) / WTZ;
-  const int ntiles = ntx * ntx * ntz;
-  return ntiles < 128 ? ntiles : 128;
+// Chunking of the weight-gradient reduction: about 2048 workgroups over the (co, ci) block
+// pairs, every chunk holding at least one tile.
+static void wgrad_split(int ks, int cin, int cout, int n, int& chunks, int& per) {
+  int ntiles;
+  int target;
+  if (mfma_layer(ks, cin, cout)) {
+    ntiles = wtiles(n);
+    const int pairs = (cout / 16) * (cin == 1 ? 1 : cin / 16);
+    target = (2048 + pairs - 1) / pairs;
+  } else {
+    const int ntx = (n + TS - 1) / TS, ntz = (n + WTZ - 1) / WTZ;
+    ntiles = ntx * ntx * ntz;
+    target = 128;
+  }
+  chunks = std::max(1, std::min(ntiles, target));
+  per = (ntiles + chunks - 1) / chunks;
+  chunks = (ntiles + per - 1) / per;
+}
+
+static int wgrad_slices(int chunks) { return std::min(chunks, 32); }
+
+void wgrad_workspace(int ks, int cin, int cout, int n, size_t& pw_floats, size_t& pb_floats, size_t& q_floats) {
+  int chunks, per;
+  wgrad_split(ks, cin, cout, n, chunks, per);
+  const size_t nw = size_t(cout) * cin * ks * ks * ks;
+  pw_floats = size_t(chunks) * nw;
+  pb_floats = size_t(chunks) * cout;
+  q_floats = size_t(wgrad_slices(chunks)) * (nw + cout);
 }
 
 hipError_t conv_bwd_w(int ks, const float* x0, int c0, const float* x1, int cin, const float* g, const float* y,
-                      int cout, int n, float* pw, float* pb, float* gw, float* gb, hipStream_t s) {
-  const int ntx = (n + TS - 1) / TS, ntz = (n + WTZ - 1) / WTZ;
-  const int ntiles = ntx * ntx * ntz;
-  const int chunks = weight_grad_chunks(n);
-  const int per = (ntiles + chunks - 1) / chunks;
-  const int nco = (cout + 15) / 16, nci = (cin + 15) / 16;
-  if (mfma_ok(ks, cin, cout)) {
-    const dim3 gq(unsigned(chunks), unsigned(((nco + 1) / 2) * ((nci + 1) / 2)));
-    hipLaunchKernelGGL(k_conv_bwd_w_mfma, gq, dim3(256), 0, s, x0, c0, x1, cin, g, y, cout, n, per, pw);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bias_partial, dim3(unsigned(chunks), unsigned(cout)), dim3(256), 0, s, g, y, cout, n, per,
-                       pb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nw = cout * cin * 27;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks(size_t(nw + cout))), dim3(256), 0, s, pw, pb, chunks, nw, cout,
-                       gw, gb);
-    return hipGetLastError();
+                      int cout, int n, float* pw, float* pb, float* q, float* gw, float* gb, hipStream_t s) {
+  int chunks, per;
+  wgrad_split(ks, cin, cout, n, chunks, per);
+  const int nw = cout * cin * ks * ks * ks;
+  if (y && mfma_layer(ks, cin, cout)) {   // the matrix-core kernels take the ReLU mask
+    if (cin == 1)
+      hipLaunchKernelGGL(k_conv_bwd_w_mfma_c1, dim3(unsigned(chunks), unsigned(cout / 16)), dim3(256), 0, s, x0, g, y,
+                         cout, n, per, pw, pb);
+    else
+      hipLaunchKernelGGL(k_conv_bwd_w_mfma, dim3(unsigned(chunks), unsigned((cout / 16) * (cin / 16))), dim3(256), 0,
+                         s, x0, c0, x1, cin, g, y, cout, n, per, pw, pb);
+  } else {
+    const int nco = (cout + 15) / 16, nci = (cin + 15) / 16;
+    const dim3 grid(unsigned(chunks), unsigned(nco * nci));
+    if (ks == 3)
+      hipLaunchKernelGGL(k_conv_bwd_w<3>, grid, dim3(256), 0, s, x0, c0, x1, cin, g, y, cout, n, per, pw, pb);
+    else
+      hipLaunchKernelGGL(k_conv_bwd_w<1>, grid, dim3(256), 0, s, x0, c0, x1, cin, g, y, cout, n, per, pw, pb);
   }
-  const dim3 grid(unsigned(chunks), unsigned(nco * nci));
-  if (ks == 3)
-    hipLaunchKernelGGL(k_conv_bwd_w<3>, grid, dim3(256), 0, s, x0, c0, x1, cin, g, y, cout, n, per, pw, pb);
-  else
-    hipLaunchKernelGGL(k_conv_bwd_w<1>, grid, dim3(256), 0, s, x0, c0, x1, cin, g, y, cout, n, per, pw, pb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nw = cout * cin * ks * ks * ks;
-  hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks(size_t(nw + cout))), dim3(256), 0, s, pw, pb, chunks, nw, cout, gw,
-                     gb);
+  const int slices = wgrad_slices(chunks);
+  hipLaunchKernelGGL(k_reduce_slices, dim3(blocks(size_t(nw + cout)), unsigned(slices)), dim3(256), 0, s, pw, pb,
+                     chunks, nw, cout, slices, q);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_slices, dim3(blocks(size_t(nw + cout))), dim3(256), 0, s, q, nw, cout, slices, gw, gb);
   return hipGetLastError();
 }
 
