@@ -568,42 +568,48 @@ struct WTileRegs {
 
 // Load (into registers) the tile's output-gradient block of channels co0 .. co0 + 15 with
 // the layer output y (for the ReLU mask) and its input channels ci0 .. ci0 + nci - 1 (nci =
-// 16, or 1 for the single-channel first layer).  Loads are unconditional (out-of-range
-// elements read a valid address) and their values are not touched here, so that the loads
-// of the next tile stay in flight while the current one is multiplied; validity is kept as
-// bit masks and applied when the tile is stored.
-__device__ __forceinline__ void wtile_load(WTileRegs& r, const float* x0, int c0, const float* x1, const float* g,
-                                           const float* y, int co0, int ci0, int nci, int n, int x0t, int y0t,
-                                           int z0t, size_t vol) {
-  r.va = 0;
-  r.vb = 0;
+// 16, or 1 for the single-channel first layer) of x.  Loads are unconditional (out-of-range
+// elements read a valid address) and their values are not touched here, so that many stay
+// in flight together; validity is kept as bit masks and applied when the tile is stored.
+// Addresses are a wave-uniform base plus a 32-bit element offset.
+template <bool LOAD_A = true, bool LOAD_B = true>
+__device__ __forceinline__ void wtile_load(WTileRegs& r, const float* x, const float* g, const float* y, int co0,
+                                           int ci0, int nci, int n, int x0t, int y0t, int z0t, size_t vol) {
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const unsigned nn = unsigned(n) * unsigned(n);
+  if (LOAD_A) r.va = 0;
+  if (LOAD_B) r.vb = 0;
 #pragma unroll
-  for (int k = 0; k < WA_PER; ++k) {
-    const int it = threadIdx.x + 256 * k;
-    const int co = co0 + (it >> 6), col = it & 63;
-    const int gy = y0t + (col >> 3), gx = x0t + (col & 7);
+  for (int k = 0; k < (LOAD_A ? WA_PER : 0); ++k) {
+    // item it = 256 k + 64 wave + lane: channel co0 + 4 k + wave, column lane
+    const size_t cofs = size_t(co0 + 4 * k + wave) * vol;
+    const float* gb = g + cofs;
+    const float* yb = y + cofs;
+    const int gy = y0t + (lane >> 3), gx = x0t + (lane & 7);
 #pragma unroll
     for (int z = 0; z < 4; ++z) {
       const int gz = z0t + z;
       const bool in = gz < n && gy < n && gx < n;
-      const size_t a = size_t(co) * vol + (in ? (size_t(gz) * n + gy) * n + gx : 0);
-      r.g[k][z] = g[a];
-      r.y[k][z] = y[a];
+      const unsigned o = in ? unsigned(gz) * nn + unsigned(gy) * unsigned(n) + unsigned(gx) : 0u;
+      r.g[k][z] = gb[o];
+      r.y[k][z] = yb[o];
       r.va |= unsigned(in) << (4 * k + z);
     }
   }
+  const float* xb = x + size_t(ci0) * vol;
 #pragma unroll
-  for (int k = 0; k < WB_PER; ++k) {
+  for (int k = 0; k < (LOAD_B ? WB_PER : 0); ++k) {
     const int it = threadIdx.x + 256 * k;
     const int c = it / 100, cp = it % 100;
     const int gy = y0t + cp / 10 - 1, gx = x0t + cp % 10 - 1;
     const bool inc = c < nci && unsigned(gy) < unsigned(n) && unsigned(gx) < unsigned(n);
-    const float* src = chan(x0, c0, x1, ci0 + min(c, nci - 1), vol);
+    const unsigned cofs = unsigned(min(c, nci - 1)) * unsigned(vol);
 #pragma unroll
     for (int hz = 0; hz < 6; ++hz) {
       const int gz = z0t + hz - 1;
       const bool in = inc && unsigned(gz) < unsigned(n);
-      r.x[k][hz] = src[in ? (size_t(gz) * n + gy) * n + gx : 0];
+      r.x[k][hz] = xb[in ? cofs + unsigned(gz) * nn + unsigned(gy) * unsigned(n) + unsigned(gx) : cofs];
       r.vb |= static_cast<unsigned long long>(in) << (6 * k + hz);
     }
   }
@@ -669,17 +675,32 @@ __device__ __forceinline__ void wtile_bias(const float (&bsum)[WA_PER], float* r
 
 // Layouts of the 16-channel weight-gradient kernel, which uses v_mfma_f32_16x16x32_bf16 with
 // K = 32 voxels (one y-row of the tile plane x 4 z; lane group q holds columns 2q, 2q + 1):
-//   A (masked output gradient), hi and lo: [32 column pairs][16 co][2 columns x 4 z], pair
-//     stride PA_S shorts;
-//   B (layer input): [100 halo columns][3 windows][16 ci][hi 4 z | lo 4 z], halo-column
-//     stride PB_S shorts.
+//   A (masked output gradient), hi and lo planes: [32 column pairs][16 co][2 columns x 4 z],
+//     pair stride PA_S shorts;
+//   B (layer input), hi and lo planes: [100 halo columns][16 ci][8 z (the 6 halo z, then 0)],
+//     halo-column stride PB_S shorts.  A tap's four z (dz .. dz + 3) are cut from a lane's
+//     8-z group with a funnel shift for odd dz, so one read serves the three dz taps.
 constexpr int PA_S = 136;           // 128 + 8: staging writes along x are conflict-free
-constexpr int PB_S = 392;           // 3 * 16 * 8 + 8, likewise
+constexpr int PB_S = 136;           // 16 * 8 + 8, likewise
 
+__device__ __forceinline__ bf16x8 zwindow(const uint4 c0, const uint4 c1, int dz) {
+  uint4 w;
+  if (dz == 0) {
+    w = make_uint4(c0.x, c0.y, c1.x, c1.y);
+  } else if (dz == 2) {
+    w = make_uint4(c0.y, c0.z, c1.y, c1.z);
+  } else {
+    w = make_uint4(__builtin_amdgcn_alignbit(c0.y, c0.x, 16), __builtin_amdgcn_alignbit(c0.z, c0.y, 16),
+                   __builtin_amdgcn_alignbit(c1.y, c1.x, 16), __builtin_amdgcn_alignbit(c1.z, c1.y, 16));
+  }
+  return *reinterpret_cast<const bf16x8*>(&w);
+}
+
+template <bool STORE_A, bool STORE_B>
 __device__ __forceinline__ void wtile_store32(const WTileRegs& r, unsigned short* ah, unsigned short* al,
-                                              unsigned short* bx, float (&bsum)[WA_PER]) {
+                                              unsigned short* bh, unsigned short* bl, float (&bsum)[WA_PER]) {
 #pragma unroll
-  for (int k = 0; k < WA_PER; ++k) {
+  for (int k = 0; k < (STORE_A ? WA_PER : 0); ++k) {
     const int it = threadIdx.x + 256 * k;
     const int co = it >> 6, col = it & 63;
     float v[4];
@@ -695,116 +716,118 @@ __device__ __forceinline__ void wtile_store32(const WTileRegs& r, unsigned short
     *reinterpret_cast<uint2*>(&al[o]) = lo;
   }
 #pragma unroll
-  for (int k = 0; k < WB_PER; ++k) {
+  for (int k = 0; k < (STORE_B ? WB_PER : 0); ++k) {
     const int it = threadIdx.x + 256 * k;
     const int c = it / 100, cp = it % 100;
     if (c >= 16) continue;
     unsigned h[6], l[6];
 #pragma unroll
     for (int hz = 0; hz < 6; ++hz) split_bf16(wtile_x(r, k, hz), h[hz], l[hz]);
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-      *reinterpret_cast<uint4*>(&bx[cp * PB_S + (w * 16 + c) * 8]) =
-          make_uint4(h[w] | (h[w + 1] << 16), h[w + 2] | (h[w + 3] << 16), l[w] | (l[w + 1] << 16),
-                     l[w + 2] | (l[w + 3] << 16));
+    *reinterpret_cast<uint4*>(&bh[cp * PB_S + c * 8]) =
+        make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), 0u);
+    *reinterpret_cast<uint4*>(&bl[cp * PB_S + c * 8]) =
+        make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), 0u);
   }
 }
 
 // Weight-gradient partials of a 16 x 16 (co, ci) block over a chunk of tiles:
-// pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1]; wave w owns taps w, w + 4, ...
-// Each 32-voxel step takes three products (hi hi, hi lo, lo hi).  The workgroup with ci
-// block 0 also writes the bias partial pb[chunk][co].  The next tile's loads are in flight
-// while the current one is multiplied.
-__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(const float* __restrict__ x0, int c0,
-                                                         const float* __restrict__ x1, int cin,
+// pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1].  Wave w takes tile rows 2w and
+// 2w + 1 for all 27 taps; each 32-voxel step takes three products (hi hi, hi lo, lo hi); the
+// four waves' sums are added in the fixed order (w0 + w1) + (w2 + w3).  The workgroup with
+// ci block 0 also writes the bias partial pb[chunk][co].
+__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(const float* __restrict__ x0, int cin,
                                                          const float* __restrict__ g, const float* __restrict__ y,
                                                          int cout, int n, int tiles_per_chunk,
                                                          float* __restrict__ pw, float* __restrict__ pb) {
-  __shared__ __attribute__((aligned(16))) unsigned short ah[32 * PA_S];
-  __shared__ __attribute__((aligned(16))) unsigned short al[32 * PA_S];
-  __shared__ __attribute__((aligned(16))) unsigned short bx[100 * PB_S];
+  constexpr int AS = 32 * PA_S, BS = 100 * PB_S;   // shorts per plane
+  __shared__ __attribute__((aligned(16))) unsigned short smem[2 * AS + 2 * BS];
+  unsigned short* ah = smem;
+  unsigned short* al = smem + AS;
+  unsigned short* bh = smem + 2 * AS;
+  unsigned short* bl = smem + 2 * AS + BS;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int m = lane & 15, kg = lane >> 4;
   const int nco = cout / 16;
   const int cb = blockIdx.y % nco, ib = blockIdx.y / nco;
   const int ntiles = wtiles(n);
   const size_t vol = size_t(n) * n * n;
-  // this wave's taps and their offsets within B
-  int toff[7];
+  f32x4 acc[27];
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    const int tap = min(wave + 4 * j, 26);
-    toff[j] = (((tap / 3) % 3) * 10 + tap % 3) * PB_S + (tap / 9) * 128;
-  }
-  const int ntap = wave == 3 ? 6 : 7;
-  f32x4 acc[7];
-#pragma unroll
-  for (int j = 0; j < 7; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < 27; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   float bsum[WA_PER] = {0.0f, 0.0f, 0.0f, 0.0f};
-  const int tile0 = blockIdx.x * tiles_per_chunk;
-  const int tile_end = min(ntiles, tile0 + tiles_per_chunk);
-  WTileRegs r;
-  if (tile0 < tile_end) {
+  const int tile_end = min(ntiles, int(blockIdx.x + 1) * tiles_per_chunk);
+  for (int tile = blockIdx.x * tiles_per_chunk; tile < tile_end; ++tile) {
     int x0t, y0t, z0t;
-    wtile_origin(tile0, n, x0t, y0t, z0t);
-    wtile_load(r, x0, c0, x1, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
-  }
-  for (int tile = tile0; tile < tile_end; ++tile) {
+    wtile_origin(tile, n, x0t, y0t, z0t);
+    // the gradient block is loaded while other waves may still multiply the previous tile;
+    // the input block after it, to bound the registers in flight
+    WTileRegs r;
+    wtile_load<true, false>(r, x0, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
     __syncthreads();
-    wtile_store32(r, ah, al, bx, bsum);
+    wtile_store32<true, false>(r, ah, al, bh, bl, bsum);
+    wtile_load<false, true>(r, x0, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
+    wtile_store32<false, true>(r, ah, al, bh, bl, bsum);
     __syncthreads();
-    if (tile + 1 < tile_end) {
-      int x0t, y0t, z0t;
-      wtile_origin(tile + 1, n, x0t, y0t, z0t);
-      wtile_load(r, x0, c0, x1, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
-    }
-#pragma unroll 2
-    for (int row = 0; row < 8; ++row) {
-      const int pr = 4 * row + kg;
-      const bf16x8 a_hi = lds8(&ah[pr * PA_S + m * 8]);
-      const bf16x8 a_lo = lds8(&al[pr * PA_S + m * 8]);
-      const int base = (row * 10 + 2 * kg) * PB_S + m * 8;
-      bf16x8 b_hi[7], b_lo[7];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        if (j == 6 && ntap == 6) break;
-        const uint4 r0 = *reinterpret_cast<const uint4*>(&bx[base + toff[j]]);
-        const uint4 r1 = *reinterpret_cast<const uint4*>(&bx[base + toff[j] + PB_S]);
-        const uint4 bh4 = make_uint4(r0.x, r0.y, r1.x, r1.y), bl4 = make_uint4(r0.z, r0.w, r1.z, r1.w);
-        b_hi[j] = *reinterpret_cast<const bf16x8*>(&bh4);
-        b_lo[j] = *reinterpret_cast<const bf16x8*>(&bl4);
-      }
+    for (int rr = 0; rr < 2; ++rr) {
+      const int row = 2 * wave + rr;
+      const bf16x8 a_hi = lds8(&ah[(4 * row + kg) * PA_S + m * 8]);
+      const bf16x8 a_lo = lds8(&al[(4 * row + kg) * PA_S + m * 8]);
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        if (j == 6 && ntap == 6) break;
-        acc[j] = mfma32(a_hi, b_hi[j], acc[j]);
-      }
+      for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        if (j == 6 && ntap == 6) break;
-        acc[j] = mfma32(a_hi, b_lo[j], acc[j]);
-      }
+        for (int dx = 0; dx < 3; ++dx) {
+          // keeps the scheduler from hoisting every LDS read of the row (register pressure)
+          __builtin_amdgcn_sched_barrier(0);
+          const int o = ((row + dy) * 10 + 2 * kg + dx) * PB_S + m * 8;
+          const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
+          const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
+          const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
+          const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        if (j == 6 && ntap == 6) break;
-        acc[j] = mfma32(a_lo, b_hi[j], acc[j]);
-      }
+          for (int dz = 0; dz < 3; ++dz) {
+            const int tap = (dz * 3 + dy) * 3 + dx;
+            const bf16x8 b_hi = zwindow(h0, h1, dz), b_lo = zwindow(l0, l1, dz);
+            acc[tap] = mfma32(a_hi, b_hi, acc[tap]);
+            acc[tap] = mfma32(a_hi, b_lo, acc[tap]);
+            acc[tap] = mfma32(a_lo, b_hi, acc[tap]);
+          }
+        }
     }
   }
-  const int ci = 16 * ib + m;
+  // (w0 + w1) + (w2 + w3) through LDS
+  float* red = reinterpret_cast<float*>(smem);
+  __syncthreads();
+  if (wave & 1) {
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    if (j == 6 && ntap == 6) break;
-    const int tap = wave + 4 * j;
+    for (int j = 0; j < 27; ++j) *reinterpret_cast<f32x4*>(&red[((wave >> 1) * 27 + j) * 256 + lane * 4]) = acc[j];
+  }
+  __syncthreads();
+  if (!(wave & 1)) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int co = 16 * cb + 4 * kg + i;
-      pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + tap] = acc[j][i];
+    for (int j = 0; j < 27; ++j) acc[j] += *reinterpret_cast<const f32x4*>(&red[((wave >> 1) * 27 + j) * 256 + lane * 4]);
+  }
+  __syncthreads();
+  if (wave == 2) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) *reinterpret_cast<f32x4*>(&red[j * 256 + lane * 4]) = acc[j];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int ci = 16 * ib + m;
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      const f32x4 s = acc[j] + *reinterpret_cast<const f32x4*>(&red[j * 256 + lane * 4]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = 16 * cb + 4 * kg + i;
+        pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + j] = s[i];
+      }
     }
   }
   if (ib == 0) {
     __syncthreads();
-    wtile_bias(bsum, reinterpret_cast<float*>(bx), pb + size_t(blockIdx.x) * cout + 16 * cb);
+    wtile_bias(bsum, red, pb + size_t(blockIdx.x) * cout + 16 * cb);
   }
 }
 
@@ -840,7 +863,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mfma_c1(const float* __restr
   if (tile0 < tile_end) {
     int x0t, y0t, z0t;
     wtile_origin(tile0, n, x0t, y0t, z0t);
-    wtile_load(r, x, 1, nullptr, g, y, 16 * cb, 0, 1, n, x0t, y0t, z0t, vol);
+    wtile_load(r, x, g, y, 16 * cb, 0, 1, n, x0t, y0t, z0t, vol);
   }
   for (int tile = tile0; tile < tile_end; ++tile) {
     __syncthreads();
@@ -849,7 +872,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mfma_c1(const float* __restr
     if (tile + 1 < tile_end) {
       int x0t, y0t, z0t;
       wtile_origin(tile + 1, n, x0t, y0t, z0t);
-      wtile_load(r, x, 1, nullptr, g, y, 16 * cb, 0, 1, n, x0t, y0t, z0t, vol);
+      wtile_load(r, x, g, y, 16 * cb, 0, 1, n, x0t, y0t, z0t, vol);
     }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
@@ -1097,15 +1120,16 @@ hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const
   return hipGetLastError();
 }
 
-// Chunking of the weight-gradient reduction: about 2048 workgroups over the (co, ci) block
-// pairs, every chunk holding at least one tile.
+// Chunking of the weight-gradient reduction: about 1024 (2048 for the single-channel kernel)
+// workgroups over the (co, ci) block pairs, every chunk holding at least one tile.
 static void wgrad_split(int ks, int cin, int cout, int n, int& chunks, int& per) {
   int ntiles;
   int target;
   if (mfma_layer(ks, cin, cout)) {
     ntiles = wtiles(n);
     const int pairs = (cout / 16) * (cin == 1 ? 1 : cin / 16);
-    target = (2048 + pairs - 1) / pairs;
+    const int wgs = cin == 1 ? 2048 : 1024;
+    target = (wgs + pairs - 1) / pairs;
   } else {
     const int ntx = (n + TS - 1) / TS, ntz = (n + WTZ - 1) / WTZ;
     ntiles = ntx * ntx * ntz;
@@ -1132,13 +1156,13 @@ hipError_t conv_bwd_w(int ks, const float* x0, int c0, const float* x1, int cin,
   int chunks, per;
   wgrad_split(ks, cin, cout, n, chunks, per);
   const int nw = cout * cin * ks * ks * ks;
-  if (y && mfma_layer(ks, cin, cout)) {   // the matrix-core kernels take the ReLU mask
+  if (y && !x1 && mfma_layer(ks, cin, cout)) {   // matrix-core kernels: one input tensor, ReLU mask
     if (cin == 1)
       hipLaunchKernelGGL(k_conv_bwd_w_mfma_c1, dim3(unsigned(chunks), unsigned(cout / 16)), dim3(256), 0, s, x0, g, y,
                          cout, n, per, pw, pb);
     else
       hipLaunchKernelGGL(k_conv_bwd_w_mfma, dim3(unsigned(chunks), unsigned((cout / 16) * (cin / 16))), dim3(256), 0,
-                         s, x0, c0, x1, cin, g, y, cout, n, per, pw, pb);
+                         s, x0, cin, g, y, cout, n, per, pw, pb);
   } else {
     const int nco = (cout + 15) / 16, nci = (cin + 15) / 16;
     const dim3 grid(unsigned(chunks), unsigned(nco * nci));
