@@ -953,58 +953,128 @@ __global__ void k_weight_layout(const __hip_bfloat16* __restrict__ w, int cout, 
 }
 
 // ------------------------------------------------------------------ resampling
-__global__ void k_pool2(const float* __restrict__ x, float* __restrict__ y, int c, int n) {
-  const int h = n / 2;
-  const size_t total = size_t(c) * h * h * h;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int xx = int(i % h), yy = int((i / h) % h), zz = int((i / (size_t(h) * h)) % h);
-  const size_t ch = i / (size_t(h) * h * h);
-  const float* src = x + ch * size_t(n) * n * n;
+// One thread per output voxel of channel blockIdx.y (32-bit index arithmetic).
+__global__ void k_pool2(const float* __restrict__ x, float* __restrict__ y, int n) {
+  const unsigned h = unsigned(n) / 2, hv = h * h * h;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hv) return;
+  const unsigned xx = i % h, yy = (i / h) % h, zz = i / (h * h), un = unsigned(n);
+  const float* src = x + size_t(blockIdx.y) * un * un * un + (2 * zz * un + 2 * yy) * un + 2 * xx;
   float s = 0.0f;
-  for (int a = 0; a < 2; ++a)
-    for (int bq = 0; bq < 2; ++bq)
-      for (int cq = 0; cq < 2; ++cq) s += src[(size_t(2 * zz + a) * n + 2 * yy + bq) * n + 2 * xx + cq];
-  y[i] = 0.125f * s;
+  for (unsigned a = 0; a < 2; ++a)
+    for (unsigned bq = 0; bq < 2; ++bq)
+      for (unsigned cq = 0; cq < 2; ++cq) s += src[(a * un + bq) * un + cq];
+  y[size_t(blockIdx.y) * hv + i] = 0.125f * s;
 }
 
-// y (n^3, c channels) = nearest 2x upsampling of x ((n/2)^3)
-__global__ void k_up2(const float* __restrict__ x, float* __restrict__ y, int c, int n) {
-  const int h = n / 2;
-  const size_t total = size_t(c) * n * n * n;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int xx = int(i % n), yy = int((i / n) % n), zz = int((i / (size_t(n) * n)) % n);
-  const size_t ch = i / (size_t(n) * n * n);
-  y[i] = x[ch * size_t(h) * h * h + (size_t(zz / 2) * h + yy / 2) * h + xx / 2];
+// y (n^3) = nearest 2x upsampling of x ((n/2)^3)
+__global__ void k_up2(const float* __restrict__ x, float* __restrict__ y, int n) {
+  const unsigned un = unsigned(n), h = un / 2, nv = un * un * un;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const unsigned xx = i % un, yy = (i / un) % un, zz = i / (un * un);
+  y[size_t(blockIdx.y) * nv + i] = x[size_t(blockIdx.y) * h * h * h + ((zz / 2) * h + yy / 2) * h + xx / 2];
 }
 
 // gx ((n/2)^3) = sum of g (n^3) over each 2x2x2 block
-__global__ void k_up2_bwd(const float* __restrict__ g, float* __restrict__ gx, int c, int n) {
-  const int h = n / 2;
-  const size_t total = size_t(c) * h * h * h;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int xx = int(i % h), yy = int((i / h) % h), zz = int((i / (size_t(h) * h)) % h);
-  const size_t ch = i / (size_t(h) * h * h);
-  const float* src = g + ch * size_t(n) * n * n;
+__global__ void k_up2_bwd(const float* __restrict__ g, float* __restrict__ gx, int n) {
+  const unsigned h = unsigned(n) / 2, hv = h * h * h;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= hv) return;
+  const unsigned xx = i % h, yy = (i / h) % h, zz = i / (h * h), un = unsigned(n);
+  const float* src = g + size_t(blockIdx.y) * un * un * un + (2 * zz * un + 2 * yy) * un + 2 * xx;
   float s = 0.0f;
-  for (int a = 0; a < 2; ++a)
-    for (int bq = 0; bq < 2; ++bq)
-      for (int cq = 0; cq < 2; ++cq) s += src[(size_t(2 * zz + a) * n + 2 * yy + bq) * n + 2 * xx + cq];
-  gx[i] = s;
+  for (unsigned a = 0; a < 2; ++a)
+    for (unsigned bq = 0; bq < 2; ++bq)
+      for (unsigned cq = 0; cq < 2; ++cq) s += src[(a * un + bq) * un + cq];
+  gx[size_t(blockIdx.y) * hv + i] = s;
 }
 
 // gx (n^3) = g((n/2)^3)/8 at the coarse voxel + add (n^3)
 __global__ void k_pool2_bwd_add(const float* __restrict__ g, const float* __restrict__ add, float* __restrict__ gx,
-                                int c, int n) {
-  const int h = n / 2;
-  const size_t total = size_t(c) * n * n * n;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int xx = int(i % n), yy = int((i / n) % n), zz = int((i / (size_t(n) * n)) % n);
-  const size_t ch = i / (size_t(n) * n * n);
-  gx[i] = 0.125f * g[ch * size_t(h) * h * h + (size_t(zz / 2) * h + yy / 2) * h + xx / 2] + add[i];
+                                int n) {
+  const unsigned un = unsigned(n), h = un / 2, nv = un * un * un;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const unsigned xx = i % un, yy = (i / un) % un, zz = i / (un * un);
+  const size_t o = size_t(blockIdx.y) * nv + i;
+  gx[o] = 0.125f * g[size_t(blockIdx.y) * h * h * h + ((zz / 2) * h + yy / 2) * h + xx / 2] + add[o];
+}
+
+// Four consecutive x per thread (n a multiple of 4): float4 stores.
+__global__ void k_up2_v4(const float* __restrict__ x, float* __restrict__ y, int n) {
+  const unsigned un = unsigned(n), h = un / 2, q = un / 4, nq = q * un * un;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const unsigned xq = i % q, yy = (i / q) % un, zz = i / (q * un);
+  const float* src = x + size_t(blockIdx.y) * h * h * h + ((zz / 2) * h + yy / 2) * h + 2 * xq;
+  const float a = src[0], b = src[1];
+  reinterpret_cast<float4*>(y + size_t(blockIdx.y) * un * un * un)[i] = make_float4(a, a, b, b);
+}
+
+__global__ void k_pool2_bwd_add_v4(const float* __restrict__ g, const float* __restrict__ add, float* __restrict__ gx,
+                                   int n) {
+  const unsigned un = unsigned(n), h = un / 2, q = un / 4, nq = q * un * un;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const unsigned xq = i % q, yy = (i / q) % un, zz = i / (q * un);
+  const float* src = g + size_t(blockIdx.y) * h * h * h + ((zz / 2) * h + yy / 2) * h + 2 * xq;
+  const float a = 0.125f * src[0], b = 0.125f * src[1];
+  const size_t o = size_t(blockIdx.y) * nq + i;
+  const float4 s = reinterpret_cast<const float4*>(add)[o];
+  reinterpret_cast<float4*>(gx)[o] = make_float4(a + s.x, a + s.y, b + s.z, b + s.w);
+}
+
+// ------------------------------------------------------------------ 1x1 output layer (cout = 1)
+// Weight-gradient partials of the 1x1 layer: pw[chunk][ci] = sum_v g[v] x[ci][v] and
+// pb[chunk] = sum_v g[v] over the chunk's voxels (thread-strided sums, then a fixed tree).
+__global__ __launch_bounds__(256) void k_wgrad1x1(const float* __restrict__ x, int cin, const float* __restrict__ g,
+                                                  unsigned nv, unsigned per, float* __restrict__ pw,
+                                                  float* __restrict__ pb) {
+  __shared__ float red[17][256];
+  float acc[17];
+#pragma unroll
+  for (int c = 0; c < 17; ++c) acc[c] = 0.0f;
+  const unsigned v0 = blockIdx.x * per, v1 = min(nv, v0 + per);
+  for (unsigned v = v0 + threadIdx.x; v < v1; v += 256) {
+    const float gv = g[v];
+    acc[16] += gv;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < cin) acc[c] += gv * x[size_t(c) * nv + v];
+  }
+#pragma unroll
+  for (int c = 0; c < 17; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (int(threadIdx.x) < off)
+#pragma unroll
+      for (int c = 0; c < 17; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < unsigned(cin)) pw[size_t(blockIdx.x) * cin + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == 0) pb[blockIdx.x] = red[16][0];
+}
+
+
+// y[v] = res[v] + b + sum_ci w[ci] x[ci][v]; one thread per voxel, channels summed in order.
+__global__ void k_conv1x1_fwd(const float* __restrict__ x, int cin, const __hip_bfloat16* __restrict__ w,
+                              const float* __restrict__ b, const float* __restrict__ res, float* __restrict__ y,
+                              unsigned nv) {
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  float s = b[0];
+  for (int c = 0; c < cin; ++c) s += __bfloat162float(w[c]) * x[size_t(c) * nv + v];
+  y[v] = res ? res[v] + s : s;
+}
+
+// gx[ci][v] = w[ci] g[v]
+__global__ void k_conv1x1_bwd_data(const float* __restrict__ g, const __hip_bfloat16* __restrict__ w, int cin,
+                                   float* __restrict__ gx, unsigned nv) {
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const float gv = g[v];
+  for (int c = 0; c < cin; ++c) gx[size_t(c) * nv + v] = __bfloat162float(w[c]) * gv;
 }
 
 // ------------------------------------------------------------------ loss and optimiser
@@ -1088,6 +1158,11 @@ hipError_t conv_fwd(int ks, const float* x0, int c0, const float* x1, int cin, c
     }
     return hipGetLastError();
   }
+  if (ks == 1 && cout == 1 && !x1 && !relu) {
+    const unsigned nv = unsigned(n) * unsigned(n) * unsigned(n);
+    hipLaunchKernelGGL(k_conv1x1_fwd, dim3(blocks(nv)), dim3(256), 0, s, x0, cin, w, b, res, out, nv);
+    return hipGetLastError();
+  }
   const int nt = (n + TS - 1) / TS;
   const dim3 grid(unsigned(nt * nt * nt), unsigned((cout + COB - 1) / COB));
   if (ks == 3)
@@ -1111,6 +1186,11 @@ hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const
     }
     return hipGetLastError();
   }
+  if (ks == 1 && cout == 1 && !y && c0 >= cin) {
+    const unsigned nv = unsigned(n) * unsigned(n) * unsigned(n);
+    hipLaunchKernelGGL(k_conv1x1_bwd_data, dim3(blocks(nv)), dim3(256), 0, s, g, w, cin, gx0, nv);
+    return hipGetLastError();
+  }
   const int nt = (n + TS - 1) / TS;
   const dim3 grid(unsigned(nt * nt * nt), unsigned((cin + COB - 1) / COB));
   if (ks == 3)
@@ -1121,7 +1201,8 @@ hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const
 }
 
 // Chunking of the weight-gradient reduction: about 1024 (2048 for the single-channel kernel)
-// workgroups over the (co, ci) block pairs, every chunk holding at least one tile.
+// workgroups over the (co, ci) block pairs (1024 chunks for a 1x1 layer, 128 for other
+// layers of the general kernel), every chunk holding at least one tile.
 static void wgrad_split(int ks, int cin, int cout, int n, int& chunks, int& per) {
   int ntiles;
   int target;
@@ -1133,7 +1214,7 @@ static void wgrad_split(int ks, int cin, int cout, int n, int& chunks, int& per)
   } else {
     const int ntx = (n + TS - 1) / TS, ntz = (n + WTZ - 1) / WTZ;
     ntiles = ntx * ntx * ntz;
-    target = 128;
+    target = ks == 1 ? 1024 : 128;
   }
   chunks = std::max(1, std::min(ntiles, target));
   per = (ntiles + chunks - 1) / chunks;
@@ -1163,6 +1244,10 @@ hipError_t conv_bwd_w(int ks, const float* x0, int c0, const float* x1, int cin,
     else
       hipLaunchKernelGGL(k_conv_bwd_w_mfma, dim3(unsigned(chunks), unsigned((cout / 16) * (cin / 16))), dim3(256), 0,
                          s, x0, cin, g, y, cout, n, per, pw, pb);
+  } else if (ks == 1 && cout == 1 && cin <= 16 && !y && !x1) {
+    const unsigned nv = unsigned(n) * unsigned(n) * unsigned(n);
+    const unsigned vper = (nv + unsigned(chunks) - 1) / unsigned(chunks);
+    hipLaunchKernelGGL(k_wgrad1x1, dim3(unsigned(chunks)), dim3(256), 0, s, x0, cin, g, nv, vper, pw, pb);
   } else {
     const int nco = (cout + 15) / 16, nci = (cin + 15) / 16;
     const dim3 grid(unsigned(chunks), unsigned(nco * nci));
@@ -1181,25 +1266,33 @@ hipError_t conv_bwd_w(int ks, const float* x0, int c0, const float* x1, int cin,
   return hipGetLastError();
 }
 
+static dim3 vox_grid(size_t voxels, int c) { return dim3(blocks(voxels), unsigned(c)); }
+
 hipError_t pool2(const float* x, float* y, int c, int n, hipStream_t s) {
   const size_t h = size_t(n / 2);
-  hipLaunchKernelGGL(k_pool2, dim3(blocks(size_t(c) * h * h * h)), dim3(256), 0, s, x, y, c, n);
+  hipLaunchKernelGGL(k_pool2, vox_grid(h * h * h, c), dim3(256), 0, s, x, y, n);
   return hipGetLastError();
 }
 
 hipError_t up2(const float* x, float* y, int c, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_up2, dim3(blocks(size_t(c) * n * n * n)), dim3(256), 0, s, x, y, c, n);
+  if (n % 4 == 0)
+    hipLaunchKernelGGL(k_up2_v4, vox_grid(size_t(n) * n * n / 4, c), dim3(256), 0, s, x, y, n);
+  else
+    hipLaunchKernelGGL(k_up2, vox_grid(size_t(n) * n * n, c), dim3(256), 0, s, x, y, n);
   return hipGetLastError();
 }
 
 hipError_t up2_bwd(const float* g, float* gx, int c, int n, hipStream_t s) {
   const size_t h = size_t(n / 2);
-  hipLaunchKernelGGL(k_up2_bwd, dim3(blocks(size_t(c) * h * h * h)), dim3(256), 0, s, g, gx, c, n);
+  hipLaunchKernelGGL(k_up2_bwd, vox_grid(h * h * h, c), dim3(256), 0, s, g, gx, n);
   return hipGetLastError();
 }
 
 hipError_t pool2_bwd_add(const float* g, const float* add, float* gx, int c, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool2_bwd_add, dim3(blocks(size_t(c) * n * n * n)), dim3(256), 0, s, g, add, gx, c, n);
+  if (n % 4 == 0)
+    hipLaunchKernelGGL(k_pool2_bwd_add_v4, vox_grid(size_t(n) * n * n / 4, c), dim3(256), 0, s, g, add, gx, n);
+  else
+    hipLaunchKernelGGL(k_pool2_bwd_add, vox_grid(size_t(n) * n * n, c), dim3(256), 0, s, g, add, gx, n);
   return hipGetLastError();
 }
 
