@@ -3,8 +3,14 @@
 shows what the trained network gains over the plain sparse-view reconstruction.
 
 Tolerances: the GPU convolves with BF16-rounded weights (the oracle rounds the same
-FP32 parameters the same way) and sums in FP32: forward rel-L2 <= 1e-5 on the network's
-correction y - x, gradients rel-L2 <= 1e-4 per layer (sums over every voxel)."""
+FP32 parameters the same way); on the matrix cores each FP32 activation or gradient is
+split into BF16 hi + lo (relative remainder <= 2^-18) and the products are summed in FP32:
+forward rel-L2 <= 1e-5 on the network's correction y - x, gradients rel-L2 <= 1e-4 per
+layer (sums over every voxel) wherever the gradient is unique: a ReLU unit whose
+pre-activation lies within the GPU path's rounding of zero (found by the oracle, see
+AMBIGUOUS_REL) may switch either way, and the gradients of its layer and of the layers before
+it are then checked to 1e-2 only.  n = 20 leaves ragged tiles in every kernel (levels of 20,
+10 and 5 voxels, the last two not multiples of 4); its case has such a unit in e1b."""
 import numpy as np
 import pytest
 
@@ -36,7 +42,31 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("n", [8, 16, 24])
+# input (oracle cache key) of every ReLU layer, in forward order
+_RELU_INPUT = {"e1a": "x", "e1b": "e1a", "e2a": "p1", "e2b": "e2a", "b_a": "p2", "b_b": "b_a", "d2a": "c2",
+               "d2b": "d2a", "d1a": "c1", "d1b": "d1a"}
+# A ReLU decision is taken in floating point: a pre-activation within the GPU path's rounding
+# of zero may land on either side (the matrix-core products carry a relative error of up to
+# 2^-18 each, about 4e-6 of a layer's mean |pre-activation| after a 27 * cin sum).  Units
+# closer to zero than AMBIGUOUS_REL * mean|z| make the gradients of their layer and of every
+# earlier layer (all of them its ancestors) non-unique.
+AMBIGUOUS_REL = 5e-6
+
+
+def _last_ambiguous_layer(theta64, cache):
+    """Index (in LAYERS order) of the last layer with a near-zero pre-activation, or -1."""
+    p = ou.unpack(theta64, True)
+    last = -1
+    for i, (name, _, _, _) in enumerate(ou.LAYERS):
+        if name not in _RELU_INPUT:
+            continue
+        z = np.abs(ou.conv3d(cache[_RELU_INPUT[name]], *p[name]))
+        if z.min() < AMBIGUOUS_REL * z.mean():
+            last = i
+    return last
+
+
+@pytest.mark.parametrize("n", [8, 16, 20, 24])
 def test_forward_matches_oracle(n):
     theta, x, _ = _case(n, 11 + n)
     net = unet.Net(n)
@@ -51,7 +81,7 @@ def test_forward_matches_oracle(n):
     net.destroy()
 
 
-@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("n", [8, 16, 20])
 def test_gradient_matches_oracle(n):
     theta, x, t = _case(n, 21 + n)
     net = unet.Net(n)
@@ -65,15 +95,23 @@ def test_gradient_matches_oracle(n):
     want, _ = ou.backward(th64, cache, gy, bf16=True)
     assert abs(loss.item() - want_loss) <= 1e-5 * want_loss
     got = g.cpu().numpy().astype(np.float64)
+    last = _last_ambiguous_layer(th64, cache)
     off = 0
-    for name, ci, co, k in ou.LAYERS:
+    bad = []
+    for i, (name, ci, co, k) in enumerate(ou.LAYERS):
         nw = co * ci * k ** 3
+        # unique result: the FP32 bar; behind a near-zero ReLU unit: still the same gradient
+        # up to that unit's flip (a few voxels' contributions)
+        tol = 1e-4 if i > last else 1e-2
         for part, sl in (("w", slice(off, off + nw)), ("b", slice(off + nw, off + nw + co))):
             err = _rel(got[sl], want[sl])
-            print(f"unet grad n={n} {name}.{part}: rel-L2 {err:.3g}", flush=True)
-            assert err <= 1e-4, (name, part, err)
+            print(f"unet grad n={n} {name}.{part}: rel-L2 {err:.3g} (bar {tol:g})", flush=True)
+            if not err <= tol:
+                bad.append((name, part, err))
         off += nw + co
     net.destroy()
+    assert not bad, bad
+    assert last < len(ou.LAYERS) - 3, "the case leaves too few layers with a unique gradient"
 
 
 def test_adam_matches_oracle():
