@@ -16,7 +16,9 @@
  * Parameters: one float32 vector of tomo_unet_param_count() values: for each layer in
  * the order above, weights [Cout][Cin][k][k][k] then bias [Cout].  The convolutions use
  * the BF16 rounding (nearest even) of the weights; activations, gradients and all sums
- * are FP32 (the loss FP64), in a fixed order: results are bitwise reproducible.
+ * are FP32 (the loss FP64), in a fixed order: results are bitwise reproducible.  On the
+ * matrix cores an FP32 operand is split into two BF16 parts (relative remainder at most
+ * 2^-18), so a product carries at most that relative error.
  * Loss: mean squared error.  Optimiser: Adam with bias correction.
  *
  * All device pointers are caller-owned, 256-byte aligned; calls are asynchronous on

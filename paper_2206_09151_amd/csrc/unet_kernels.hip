@@ -731,29 +731,37 @@ __device__ __forceinline__ void wtile_store32(const WTileRegs& r, unsigned short
 }
 
 // Weight-gradient partials of a 16 x 16 (co, ci) block over a chunk of tiles:
-// pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1].  Wave w takes tile rows 2w and
-// 2w + 1 for all 27 taps; each 32-voxel step takes three products (hi hi, hi lo, lo hi); the
-// four waves' sums are added in the fixed order (w0 + w1) + (w2 + w3).  The workgroup with
-// ci block 0 also writes the bias partial pb[chunk][co].
-__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(const float* __restrict__ x0, int cin,
-                                                         const float* __restrict__ g, const float* __restrict__ y,
-                                                         int cout, int n, int tiles_per_chunk,
-                                                         float* __restrict__ pw, float* __restrict__ pb) {
+// pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1].  Taps are dealt to the waves by
+// their (dy, dx) group g = 3 dy + dx: wave w takes groups w and w + 4 with all three dz, and
+// waves 0-2 also take group 8 at dz = w (seven taps each, six for wave 3); every wave runs
+// over all rows of the tile, one LDS read of a column's eight z serving the dz taps of a
+// group.  Each 32-voxel step takes three products (hi hi, hi lo, lo hi).  Two workgroups
+// fit a CU (72 KB of LDS each), so one's tile loads overlap the other's products.  The
+// workgroup with ci block 0 also writes the bias partial pb[chunk][co].
+__global__ __launch_bounds__(256, 2) void k_conv_bwd_w_mfma(const float* __restrict__ x0, int cin,
+                                                            const float* __restrict__ g, const float* __restrict__ y,
+                                                            int cout, int n, int tiles_per_chunk,
+                                                            float* __restrict__ pw, float* __restrict__ pb) {
   constexpr int AS = 32 * PA_S, BS = 100 * PB_S;   // shorts per plane
   __shared__ __attribute__((aligned(16))) unsigned short smem[2 * AS + 2 * BS];
   unsigned short* ah = smem;
   unsigned short* al = smem + AS;
   unsigned short* bh = smem + 2 * AS;
   unsigned short* bl = smem + 2 * AS + BS;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int m = lane & 15, kg = lane >> 4;
   const int nco = cout / 16;
   const int cb = blockIdx.y % nco, ib = blockIdx.y / nco;
   const int ntiles = wtiles(n);
   const size_t vol = size_t(n) * n * n;
-  f32x4 acc[27];
+  // B offsets of this wave's groups: (dy * 10 + dx) halo columns
+  const int g0 = wave, g1 = wave + 4;
+  const int off0 = ((g0 / 3) * 10 + g0 % 3) * PB_S, off1 = ((g1 / 3) * 10 + g1 % 3) * PB_S;
+  const int off8 = (2 * 10 + 2) * PB_S;
+  f32x4 acc[7];
 #pragma unroll
-  for (int j = 0; j < 27; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < 7; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   float bsum[WA_PER] = {0.0f, 0.0f, 0.0f, 0.0f};
   const int tile_end = min(ntiles, int(blockIdx.x + 1) * tiles_per_chunk);
   for (int tile = blockIdx.x * tiles_per_chunk; tile < tile_end; ++tile) {
@@ -768,66 +776,54 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(const float* __restrict
     wtile_load<false, true>(r, x0, g, y, 16 * cb, 16 * ib, 16, n, x0t, y0t, z0t, vol);
     wtile_store32<false, true>(r, ah, al, bh, bl, bsum);
     __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-      const int row = 2 * wave + rr;
+#pragma unroll 2
+    for (int row = 0; row < 8; ++row) {
       const bf16x8 a_hi = lds8(&ah[(4 * row + kg) * PA_S + m * 8]);
       const bf16x8 a_lo = lds8(&al[(4 * row + kg) * PA_S + m * 8]);
+      const int base = (row * 10 + 2 * kg) * PB_S + m * 8;
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
+      for (int gi = 0; gi < 2; ++gi) {
+        const int o = base + (gi ? off1 : off0);
+        const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
+        const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
+        const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
+        const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          // keeps the scheduler from hoisting every LDS read of the row (register pressure)
-          __builtin_amdgcn_sched_barrier(0);
-          const int o = ((row + dy) * 10 + 2 * kg + dx) * PB_S + m * 8;
-          const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
-          const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
-          const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
-          const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
-#pragma unroll
-          for (int dz = 0; dz < 3; ++dz) {
-            const int tap = (dz * 3 + dy) * 3 + dx;
-            const bf16x8 b_hi = zwindow(h0, h1, dz), b_lo = zwindow(l0, l1, dz);
-            acc[tap] = mfma32(a_hi, b_hi, acc[tap]);
-            acc[tap] = mfma32(a_hi, b_lo, acc[tap]);
-            acc[tap] = mfma32(a_lo, b_hi, acc[tap]);
-          }
+        for (int dz = 0; dz < 3; ++dz) {
+          const bf16x8 b_hi = zwindow(h0, h1, dz), b_lo = zwindow(l0, l1, dz);
+          f32x4& a = acc[3 * gi + dz];
+          a = mfma32(a_hi, b_hi, a);
+          a = mfma32(a_hi, b_lo, a);
+          a = mfma32(a_lo, b_hi, a);
         }
+      }
+      if (wave < 3) {
+        const int o = base + off8;
+        const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
+        const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
+        const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
+        const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
+        const bf16x8 b_hi = zwindow(h0, h1, wave), b_lo = zwindow(l0, l1, wave);
+        acc[6] = mfma32(a_hi, b_hi, acc[6]);
+        acc[6] = mfma32(a_hi, b_lo, acc[6]);
+        acc[6] = mfma32(a_lo, b_hi, acc[6]);
+      }
     }
   }
-  // (w0 + w1) + (w2 + w3) through LDS
-  float* red = reinterpret_cast<float*>(smem);
-  __syncthreads();
-  if (wave & 1) {
+  const int ci = 16 * ib + m;
 #pragma unroll
-    for (int j = 0; j < 27; ++j) *reinterpret_cast<f32x4*>(&red[((wave >> 1) * 27 + j) * 256 + lane * 4]) = acc[j];
-  }
-  __syncthreads();
-  if (!(wave & 1)) {
+  for (int j = 0; j < 7; ++j) {
+    if (j == 6 && wave == 3) break;
+    const int tap = j < 6 ? (j % 3) * 9 + (j < 3 ? g0 : g1) : wave * 9 + 8;
 #pragma unroll
-    for (int j = 0; j < 27; ++j) acc[j] += *reinterpret_cast<const f32x4*>(&red[((wave >> 1) * 27 + j) * 256 + lane * 4]);
-  }
-  __syncthreads();
-  if (wave == 2) {
-#pragma unroll
-    for (int j = 0; j < 27; ++j) *reinterpret_cast<f32x4*>(&red[j * 256 + lane * 4]) = acc[j];
-  }
-  __syncthreads();
-  if (wave == 0) {
-    const int ci = 16 * ib + m;
-#pragma unroll
-    for (int j = 0; j < 27; ++j) {
-      const f32x4 s = acc[j] + *reinterpret_cast<const f32x4*>(&red[j * 256 + lane * 4]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int co = 16 * cb + 4 * kg + i;
-        pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + j] = s[i];
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int co = 16 * cb + 4 * kg + i;
+      pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + tap] = acc[j][i];
     }
   }
   if (ib == 0) {
     __syncthreads();
-    wtile_bias(bsum, red, pb + size_t(blockIdx.x) * cout + 16 * cb);
+    wtile_bias(bsum, reinterpret_cast<float*>(smem), pb + size_t(blockIdx.x) * cout + 16 * cb);
   }
 }
 
