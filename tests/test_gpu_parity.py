@@ -175,15 +175,17 @@ def test_range_errors(dev):
         plan.grid(st, -1, 1, torch.zeros((pb.n_vox,) * 3, device=dev))
 
 
-@pytest.mark.parametrize("name", ["axis32", "sphere45", "m160"])
+@pytest.mark.parametrize("name", ["axis32", "ragged44", "pct64", "oddk16", "m160", "sphere45"])
 def test_autotuned_gridding_gives_identical_volumes(name):
     """Plan-time autotuning only picks the voxel rows per gridding thread.  On the
     single-axis path the per-voxel arithmetic is the same, so the volumes are bitwise
-    equal; on the general path the staged box (and so the FP32 box-local coordinates)
-    follows the tile's height, which moves only the rounding."""
+    equal (ragged tiles, odd view counts, the flat CT limit and odd K included); on the
+    general path the staged box (and so the FP32 box-local coordinates) follows the tile's
+    height, which moves only the rounding."""
     tomo = _tomo()
     prob = _problems.make(name)
     imgs = torch.from_numpy(prob.images).to("cuda:0")
+    axis = name != "sphere45"
     out = []
     for tune in (0, 1):
         plan = tomo.Plan(prob.params(tune=tune), prob.dirs, prob.dist, vaxes=prob.vaxes)
@@ -191,7 +193,6 @@ def test_autotuned_gridding_gives_identical_volumes(name):
         vol = torch.empty((prob.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
         plan.reconstruct(imgs, vol)
         out.append(vol.cpu().numpy())
-        axis = name != "sphere45"
         plan.destroy()
     if axis:
         assert np.array_equal(out[0], out[1])
