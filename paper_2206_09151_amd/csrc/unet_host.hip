@@ -80,6 +80,9 @@ const unsigned short* WF(const tomo_unet_s* u, int l) { return has_layout(l) ? u
 const unsigned short* WD(const tomo_unet_s* u, int l) { return has_layout(l) ? u->wd + u->off[l] : nullptr; }
 const float* B(const tomo_unet_s* u, const float* th, int l) { return th + u->off[l] + weights_of(l); }
 
+// Activations are channel-last (a voxel's channels contiguous).  The two concatenations are
+// buffers of 48 (level 1) and 96 (level 2) channels: the upsampled decoder features fill the
+// first 32 / 64 channels, and the encoder writes its output straight into the rest.
 hipError_t forward(tomo_unet_s* u, const float* th, const float* x, float* y, hipStream_t s) {
   const int n = u->n, h = n / 2, q = n / 4;
   hipError_t e;
@@ -89,55 +92,56 @@ hipError_t forward(tomo_unet_s* u, const float* th, const float* x, float* y, hi
     if (has_layout(l) &&
         (e = unet::weight_layout(W(u, l), kLayers[l].cout, kLayers[l].cin, u->wf + u->off[l], u->wd + u->off[l], s)))
       return e;
-  float* e1b = u->c1 + 32 * u->v1;   // the skip half of the level-1 concatenation
-  float* e2b = u->c2 + 64 * u->v2;
-  if ((e = unet::conv_fwd(3, x, 1, nullptr, 1, W(u, E1A), WF(u, E1A), B(u, th, E1A), u->e1a, 16, n, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->e1a, 16, nullptr, 16, W(u, E1B), WF(u, E1B), B(u, th, E1B), e1b, 16, n, 1, nullptr, s))) return e;
-  if ((e = unet::pool2(e1b, u->p1, 16, n, s))) return e;
-  if ((e = unet::conv_fwd(3, u->p1, 16, nullptr, 16, W(u, E2A), WF(u, E2A), B(u, th, E2A), u->e2a, 32, h, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->e2a, 32, nullptr, 32, W(u, E2B), WF(u, E2B), B(u, th, E2B), e2b, 32, h, 1, nullptr, s))) return e;
-  if ((e = unet::pool2(e2b, u->p2, 32, h, s))) return e;
-  if ((e = unet::conv_fwd(3, u->p2, 32, nullptr, 32, W(u, BA), WF(u, BA), B(u, th, BA), u->ba, 64, q, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->ba, 64, nullptr, 64, W(u, BB), WF(u, BB), B(u, th, BB), u->bb, 64, q, 1, nullptr, s))) return e;
-  if ((e = unet::up2(u->bb, u->c2, 64, h, s))) return e;
-  if ((e = unet::conv_fwd(3, u->c2, 96, nullptr, 96, W(u, D2A), WF(u, D2A), B(u, th, D2A), u->d2a, 32, h, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->d2a, 32, nullptr, 32, W(u, D2B), WF(u, D2B), B(u, th, D2B), u->d2b, 32, h, 1, nullptr, s))) return e;
-  if ((e = unet::up2(u->d2b, u->c1, 32, n, s))) return e;
-  if ((e = unet::conv_fwd(3, u->c1, 48, nullptr, 48, W(u, D1A), WF(u, D1A), B(u, th, D1A), u->d1a, 16, n, 1, nullptr, s))) return e;
-  if ((e = unet::conv_fwd(3, u->d1a, 16, nullptr, 16, W(u, D1B), WF(u, D1B), B(u, th, D1B), u->d1b, 16, n, 1, nullptr, s))) return e;
-  return unet::conv_fwd(1, u->d1b, 16, nullptr, 16, W(u, OUT), WF(u, OUT), B(u, th, OUT), y, 1, n, 0, x, s);
+  float* e1b = u->c1 + 32;   // channels 32..47 of the level-1 concatenation
+  float* e2b = u->c2 + 64;   // channels 64..95 of the level-2 concatenation
+  if ((e = unet::conv_fwd(3, x, 1, 1, W(u, E1A), WF(u, E1A), B(u, th, E1A), u->e1a, 16, 16, n, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->e1a, 16, 16, W(u, E1B), WF(u, E1B), B(u, th, E1B), e1b, 48, 16, n, 1, nullptr, s))) return e;
+  if ((e = unet::pool2(e1b, 48, u->p1, 16, 16, n, s))) return e;
+  if ((e = unet::conv_fwd(3, u->p1, 16, 16, W(u, E2A), WF(u, E2A), B(u, th, E2A), u->e2a, 32, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->e2a, 32, 32, W(u, E2B), WF(u, E2B), B(u, th, E2B), e2b, 96, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::pool2(e2b, 96, u->p2, 32, 32, h, s))) return e;
+  if ((e = unet::conv_fwd(3, u->p2, 32, 32, W(u, BA), WF(u, BA), B(u, th, BA), u->ba, 64, 64, q, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->ba, 64, 64, W(u, BB), WF(u, BB), B(u, th, BB), u->bb, 64, 64, q, 1, nullptr, s))) return e;
+  if ((e = unet::up2(u->bb, 64, u->c2, 96, 64, h, s))) return e;
+  if ((e = unet::conv_fwd(3, u->c2, 96, 96, W(u, D2A), WF(u, D2A), B(u, th, D2A), u->d2a, 32, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->d2a, 32, 32, W(u, D2B), WF(u, D2B), B(u, th, D2B), u->d2b, 32, 32, h, 1, nullptr, s))) return e;
+  if ((e = unet::up2(u->d2b, 32, u->c1, 48, 32, n, s))) return e;
+  if ((e = unet::conv_fwd(3, u->c1, 48, 48, W(u, D1A), WF(u, D1A), B(u, th, D1A), u->d1a, 16, 16, n, 1, nullptr, s))) return e;
+  if ((e = unet::conv_fwd(3, u->d1a, 16, 16, W(u, D1B), WF(u, D1B), B(u, th, D1B), u->d1b, 16, 16, n, 1, nullptr, s))) return e;
+  return unet::conv_fwd(1, u->d1b, 16, 16, W(u, OUT), WF(u, OUT), B(u, th, OUT), y, 1, 1, n, 0, x, s);
 }
 
-// weight + bias gradient of layer l into grad, and (optionally) its input gradient
-hipError_t layer_back(tomo_unet_s* u, int l, const float* in, const float* g, const float* yout, int n, float* grad,
-                      float* gx0, int c0, float* gx1, hipStream_t s) {
+// weight + bias gradient of layer l into grad, and (optionally) its input gradient; every
+// tensor is a view (pointer, channel count of its buffer)
+hipError_t layer_back(tomo_unet_s* u, int l, const float* in, int sin, const float* g, int sg, const float* yout,
+                      int sy, int n, float* grad, float* gx, int sgx, hipStream_t s) {
   const Layer& L = kLayers[l];
-  hipError_t e = unet::conv_bwd_w(L.ks, in, L.cin, nullptr, L.cin, g, yout, L.cout, n, u->pw, u->pb, u->q,
+  hipError_t e = unet::conv_bwd_w(L.ks, in, sin, L.cin, g, sg, yout, sy, L.cout, n, u->pw, u->pb, u->q,
                                   grad + u->off[l], grad + u->off[l] + weights_of(l), s);
-  if (e != hipSuccess || !gx0) return e;
-  return unet::conv_bwd_data(L.ks, g, yout, L.cout, W(u, l), WD(u, l), gx0, c0, gx1, L.cin, n, s);
+  if (e != hipSuccess || !gx) return e;
+  return unet::conv_bwd_data(L.ks, g, sg, yout, sy, L.cout, W(u, l), WD(u, l), gx, sgx, L.cin, n, s);
 }
 
 hipError_t backward(tomo_unet_s* u, const float* x, float* grad, hipStream_t s) {
   const int n = u->n, h = n / 2, q = n / 4;
-  float* e1b = u->c1 + 32 * u->v1;
-  float* e2b = u->c2 + 64 * u->v2;
+  float* e1b = u->c1 + 32;
+  float* e2b = u->c2 + 64;
   hipError_t e;
-  if ((e = layer_back(u, OUT, u->d1b, u->gy, nullptr, n, grad, u->g_d1b, 16, nullptr, s))) return e;
-  if ((e = layer_back(u, D1B, u->d1a, u->g_d1b, u->d1b, n, grad, u->g_d1a, 16, nullptr, s))) return e;
-  if ((e = layer_back(u, D1A, u->c1, u->g_d1a, u->d1a, n, grad, u->g_c1, 48, nullptr, s))) return e;
-  if ((e = unet::up2_bwd(u->g_c1, u->g_d2b, 32, n, s))) return e;
-  if ((e = layer_back(u, D2B, u->d2a, u->g_d2b, u->d2b, h, grad, u->g_d2a, 32, nullptr, s))) return e;
-  if ((e = layer_back(u, D2A, u->c2, u->g_d2a, u->d2a, h, grad, u->g_c2, 96, nullptr, s))) return e;
-  if ((e = unet::up2_bwd(u->g_c2, u->g_bb, 64, h, s))) return e;
-  if ((e = layer_back(u, BB, u->ba, u->g_bb, u->bb, q, grad, u->g_ba, 64, nullptr, s))) return e;
-  if ((e = layer_back(u, BA, u->p2, u->g_ba, u->ba, q, grad, u->g_p2, 32, nullptr, s))) return e;
-  if ((e = unet::pool2_bwd_add(u->g_p2, u->g_c2 + 64 * u->v2, u->g_e2b, 32, h, s))) return e;
-  if ((e = layer_back(u, E2B, u->e2a, u->g_e2b, e2b, h, grad, u->g_e2a, 32, nullptr, s))) return e;
-  if ((e = layer_back(u, E2A, u->p1, u->g_e2a, u->e2a, h, grad, u->g_p1, 16, nullptr, s))) return e;
-  if ((e = unet::pool2_bwd_add(u->g_p1, u->g_c1 + 32 * u->v1, u->g_e1b, 16, n, s))) return e;
-  if ((e = layer_back(u, E1B, u->e1a, u->g_e1b, e1b, n, grad, u->g_e1a, 16, nullptr, s))) return e;
-  return layer_back(u, E1A, x, u->g_e1a, u->e1a, n, grad, nullptr, 0, nullptr, s);
+  if ((e = layer_back(u, OUT, u->d1b, 16, u->gy, 1, nullptr, 0, n, grad, u->g_d1b, 16, s))) return e;
+  if ((e = layer_back(u, D1B, u->d1a, 16, u->g_d1b, 16, u->d1b, 16, n, grad, u->g_d1a, 16, s))) return e;
+  if ((e = layer_back(u, D1A, u->c1, 48, u->g_d1a, 16, u->d1a, 16, n, grad, u->g_c1, 48, s))) return e;
+  if ((e = unet::up2_bwd(u->g_c1, 48, u->g_d2b, 32, 32, n, s))) return e;
+  if ((e = layer_back(u, D2B, u->d2a, 32, u->g_d2b, 32, u->d2b, 32, h, grad, u->g_d2a, 32, s))) return e;
+  if ((e = layer_back(u, D2A, u->c2, 96, u->g_d2a, 32, u->d2a, 32, h, grad, u->g_c2, 96, s))) return e;
+  if ((e = unet::up2_bwd(u->g_c2, 96, u->g_bb, 64, 64, h, s))) return e;
+  if ((e = layer_back(u, BB, u->ba, 64, u->g_bb, 64, u->bb, 64, q, grad, u->g_ba, 64, s))) return e;
+  if ((e = layer_back(u, BA, u->p2, 32, u->g_ba, 64, u->ba, 64, q, grad, u->g_p2, 32, s))) return e;
+  if ((e = unet::pool2_bwd_add(u->g_p2, 32, u->g_c2 + 64, 96, u->g_e2b, 32, 32, h, s))) return e;
+  if ((e = layer_back(u, E2B, u->e2a, 32, u->g_e2b, 32, e2b, 96, h, grad, u->g_e2a, 32, s))) return e;
+  if ((e = layer_back(u, E2A, u->p1, 16, u->g_e2a, 32, u->e2a, 32, h, grad, u->g_p1, 16, s))) return e;
+  if ((e = unet::pool2_bwd_add(u->g_p1, 16, u->g_c1 + 32, 48, u->g_e1b, 16, 16, n, s))) return e;
+  if ((e = layer_back(u, E1B, u->e1a, 16, u->g_e1b, 16, e1b, 48, n, grad, u->g_e1a, 16, s))) return e;
+  return layer_back(u, E1A, x, 1, u->g_e1a, 16, u->e1a, 16, n, grad, nullptr, 0, s);
 }
 
 }  // namespace

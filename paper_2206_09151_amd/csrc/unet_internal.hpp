@@ -7,6 +7,9 @@
 
 namespace unet {
 
+// Volumes are channel-last: element (v, c) of a view (p, s) is p[v * s + c], v = (z n + y) n + x,
+// s the channel count of the underlying buffer (a multiple of 16 for multi-channel views).
+//
 // Whether a layer runs on the matrix-core kernels (3x3x3, cout in {16, 32, 64}, cin a
 // multiple of 16 up to 96, or cin == 1 for the weight gradient).
 bool mfma_layer(int ks, int cin, int cout);
@@ -14,24 +17,26 @@ bool mfma_layer(int ks, int cin, int cout);
 // forward, wd (taps reversed) for the input gradient; each holds cout * cin * 27 values.
 hipError_t weight_layout(const __hip_bfloat16* w, int cout, int cin, unsigned short* wf, unsigned short* wd,
                          hipStream_t s);
-// out[co] = act(b + conv_ks(in)) (+ res), input channels [0, c0) from x0 and [c0, cin) from x1;
-// wf (the forward layout, or null) selects the matrix-core kernel where the layer allows it.
-hipError_t conv_fwd(int ks, const float* x0, int c0, const float* x1, int cin, const __hip_bfloat16* w,
-                    const unsigned short* wf, const float* b, float* out, int cout, int n, int relu,
-                    const float* res, hipStream_t s);
-// Input gradient of a conv layer; g masked by (y > 0) unless y is null; channels [0, c0) into
-// gx0; wd (the input-gradient layout, or null) selects the matrix-core kernel.
-hipError_t conv_bwd_data(int ks, const float* g, const float* y, int cout, const __hip_bfloat16* w,
-                         const unsigned short* wd, float* gx0, int c0, float* gx1, int cin, int n, hipStream_t s);
+// out = act(b + conv_ks(x)) (+ res) for the network's layers: 3x3x3 with one input channel
+// (the first layer), 3x3x3 on the matrix cores (wf, the forward layout), or the 1x1 output
+// layer (cout = 1, res added); hipErrorInvalidValue for anything else.
+hipError_t conv_fwd(int ks, const float* x, int sx, int cin, const __hip_bfloat16* w, const unsigned short* wf,
+                    const float* b, float* out, int so, int cout, int n, int relu, const float* res, hipStream_t s);
+// Input gradient gx of a layer from its output gradient g, masked by (y > 0) for the ReLU
+// layers (matrix cores, wd the input-gradient layout) or unmasked for the 1x1 output layer.
+hipError_t conv_bwd_data(int ks, const float* g, int sg, const float* y, int sy, int cout, const __hip_bfloat16* w,
+                         const unsigned short* wd, float* gx, int sgx, int cin, int n, hipStream_t s);
 // Weight and bias gradients: fixed-order chunk partials pw / pb, slice sums q, then gw / gb.
-hipError_t conv_bwd_w(int ks, const float* x0, int c0, const float* x1, int cin, const float* g, const float* y,
+hipError_t conv_bwd_w(int ks, const float* x, int sx, int cin, const float* g, int sg, const float* y, int sy,
                       int cout, int n, float* pw, float* pb, float* q, float* gw, float* gb, hipStream_t s);
 // Workspace (floats) conv_bwd_w needs for a layer.
 void wgrad_workspace(int ks, int cin, int cout, int n, size_t& pw_floats, size_t& pb_floats, size_t& q_floats);
-hipError_t pool2(const float* x, float* y, int c, int n, hipStream_t s);
-hipError_t up2(const float* x, float* y, int c, int n, hipStream_t s);
-hipError_t up2_bwd(const float* g, float* gx, int c, int n, hipStream_t s);
-hipError_t pool2_bwd_add(const float* g, const float* add, float* gx, int c, int n, hipStream_t s);
+// Resampling of c channels (a multiple of 4) between views; n is the fine edge.
+hipError_t pool2(const float* x, int sx, float* y, int sy, int c, int n, hipStream_t s);
+hipError_t up2(const float* x, int sx, float* y, int sy, int c, int n, hipStream_t s);
+hipError_t up2_bwd(const float* g, int sg, float* gx, int sgx, int c, int n, hipStream_t s);
+hipError_t pool2_bwd_add(const float* g, int sg, const float* add, int sa, float* gx, int sgx, int c, int n,
+                         hipStream_t s);
 hipError_t mse(const float* y, const float* tg, float* gy, double* part, double* loss, size_t count, hipStream_t s);
 hipError_t adam(float* th, const float* g, float* m, float* v, int count, float lr, float b1, float b2, float eps,
                 float c1, float c2, hipStream_t s);
