@@ -484,48 +484,69 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
   // this thread's share of view n's box, into registers.  Every load reads a clamped,
   // in-bounds address (no divergent zero-initialisation, so the loads stay in flight);
   // slots outside the stack are marked in `valid` and zeroed when staged.
+  // The view-independent part of every staged chunk, computed once: its (plane, column)
+  // position in the box, the clamped detector-row term of its address, and its LDS offset.
+  // Per view only the box origin moves, so the fetch is a few integer ops per chunk.
+  int cq[PER], cpl[PER], crow[PER], cdst[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
+    const int row = y0 + j + rowoff;
+    const bool rok = e < NE && (y0 + j < N) && unsigned(row) < unsigned(M);
+    cq[i] = VEC * q;
+    cpl[i] = pl;
+    crow[i] = rok ? row * K : -1;
+    cdst[i] = e < NE ? (j * AX_BOXH + pl) * BOXP + VEC * q : -1;
+  }
+  // this thread's share of view n's box, into registers.  Every load reads a clamped,
+  // in-bounds address (no divergent zero-initialisation, so the loads stay in flight);
+  // slots outside the stack are marked in `valid` and zeroed when staged.
   auto fetch = [&](int n, int c0, int p0, uint4 (&v)[PER], unsigned& valid) {
     const InT* vbase = stack + size_t(n) * plane_sz * M;
     valid = 0u;
+    if (vec) {
+      // M and the column starts are multiples of VEC: a chunk lies wholly inside or outside a row
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int pp = p0 + cpl[i], cc = c0 + cq[i];
+        const bool ok = crow[i] >= 0 && unsigned(pp) < unsigned(K) && unsigned(cc) < unsigned(M);
+        valid |= ok ? (1u << i) : 0u;
+        const unsigned off = unsigned(max(crow[i], 0) + min(max(pp, 0), K - 1)) * unsigned(M) +
+                             unsigned(min(max(cc, 0), M - VEC));
+        v[i] = *reinterpret_cast<const uint4*>(vbase + off);
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 256 * i;
       const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
       const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + VEC * q;
-      const bool ok = e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) &&
-                      cc >= 0 && cc < M;
-      valid |= ok ? (1u << i) : 0u;
       const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
       const InT* src = vbase + (size_t(rowc) * K + ppc) * M;
-      if (vec) {
-        // M and cc are multiples of VEC: a chunk lies wholly inside or wholly outside the row
-        const int ccc = min(max(cc, 0), M - VEC);
-        v[i] = *reinterpret_cast<const uint4*>(src + ccc);
-      } else {
-        Chunk16 x;
+      Chunk16 x;
 #pragma unroll
-        for (int kk = 0; kk < VEC; ++kk) {
-          const int ce = min(max(cc + kk, 0), M - 1);
-          const float fv = from_store<InT>(src[ce]);
-          const bool ek = unsigned(cc + kk) < unsigned(M);
-          if constexpr (VEC == 4) x.f[kk] = ek ? fv : 0.0f;
-          else x.h[kk] = ek ? reinterpret_cast<const unsigned short*>(src)[ce] : (unsigned short)0;
-        }
-        v[i] = x.u;
-        if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K))
-          valid |= (1u << i);                            // partial chunks carry their own zeros
+      for (int kk = 0; kk < VEC; ++kk) {
+        const int ce = min(max(cc + kk, 0), M - 1);
+        const float fv = from_store<InT>(src[ce]);
+        const bool ek = unsigned(cc + kk) < unsigned(M);
+        if constexpr (VEC == 4) x.f[kk] = ek ? fv : 0.0f;
+        else x.h[kk] = ek ? reinterpret_cast<const unsigned short*>(src)[ce] : (unsigned short)0;
       }
+      v[i] = x.u;
+      if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K))
+        valid |= (1u << i);                              // partial chunks carry their own zeros
     }
   };
   auto stage = [&](const uint4 (&v)[PER], unsigned valid) {
+    float* boxf = &box[0][0][0];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      if (e < NE) {
-        const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
+      if (cdst[i] >= 0) {
         Chunk16 x;
         x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
-        float* dst = &box[j][pl][VEC * q];
+        float* dst = boxf + cdst[i];
 #pragma unroll
         for (int h = 0; h < VEC; h += 4)
           *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
