@@ -863,20 +863,29 @@ __global__ __launch_bounds__(256) void k_grid_cube(const InT* __restrict__ stack
     r0 = int(floor(rmin));
     p0 = flat ? 0 : int(floor(pmin));
   };
+  // The view-independent part of every staged chunk (its row, plane and column offsets in
+  // the box and its LDS offset), computed once; per view only the box origin moves.
+  int cj[PER], cpl[PER], cq[PER], cdst[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    cq[i] = VEC * (e % QN);
+    cpl[i] = (e / QN) % CB_R;
+    cj[i] = e < NE ? e / (QN * CB_R) : -1;
+    cdst[i] = e < NE ? (cj[i] * CB_R + cpl[i]) * CP + cq[i] : -1;
+  }
   auto fetch = [&](int n, int r0, int p0, int c0, uint4 (&v)[PER], unsigned& valid) {
     const InT* vbase = stack + size_t(n) * plane_sz * M;
     valid = 0u;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      const int q = e % QN, pl = (e / QN) % CB_R, j = e / (QN * CB_R);
-      const int row = r0 + j, pp = p0 + pl, cc = c0 + VEC * q;
-      const bool ok = e < NE && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) && cc >= 0 && cc < M;
+      const int row = r0 + cj[i], pp = p0 + cpl[i], cc = c0 + cq[i];
+      const bool ok = cj[i] >= 0 && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) && cc >= 0 && cc < M;
       valid |= ok ? (1u << i) : 0u;
       const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
       if (vec) {
-        const int ccc = min(max(cc, 0), M - VEC);
-        v[i] = *reinterpret_cast<const uint4*>(vbase + (size_t(rowc) * K + ppc) * M + ccc);
+        const unsigned off = unsigned(rowc * K + ppc) * unsigned(M) + unsigned(min(max(cc, 0), M - VEC));
+        v[i] = *reinterpret_cast<const uint4*>(vbase + off);
       } else {
         const InT* src = vbase + (size_t(rowc) * K + ppc) * M;
         Chunk16 x;
@@ -888,19 +897,18 @@ __global__ __launch_bounds__(256) void k_grid_cube(const InT* __restrict__ stack
           else x.h[kk] = ek ? reinterpret_cast<const unsigned short*>(src)[ce] : (unsigned short)0;
         }
         v[i] = x.u;
-        if (e < NE && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K)) valid |= (1u << i);
+        if (cj[i] >= 0 && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K)) valid |= (1u << i);
       }
     }
   };
   auto stage = [&](const uint4 (&v)[PER], unsigned valid) {
+    float* boxf = &box[0][0][0];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      if (e < NE) {
-        const int q = e % QN, pl = (e / QN) % CB_R, j = e / (QN * CB_R);
+      if (cdst[i] >= 0) {
         Chunk16 x;
         x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
-        float* dst = &box[j][pl][VEC * q];
+        float* dst = boxf + cdst[i];
 #pragma unroll
         for (int h = 0; h < VEC; h += 4)
           *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
