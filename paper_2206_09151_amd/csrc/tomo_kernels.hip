@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fft.hpp"
 #include "geom.hpp"
@@ -441,12 +442,19 @@ __device__ __forceinline__ float chunk_value<__half>(const Chunk16& c, int k) {
   return __half2float(__ushort_as_half(c.h[k]));
 }
 
+// Keeps v in a register as an opaque value: the compiler may not hoist what is computed
+// from it out of the loop it sits in (for values needed only on rarely taken paths).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <int YB, class InT>
 __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack,
                                                    const ViewGeom* __restrict__ geom,
                                                    const float* __restrict__ scale,
                                                    float* __restrict__ vol, int N, int M, int K,
-                                                   int nb, int accumulate, int flat) {
+                                                   int nb, int accumulate, int flat, double hm, double hk) {
   using B = AxisBox<InT>;
   constexpr int VEC = B::VEC, BOXW = B::BOXW, BOXP = B::BOXP;
   constexpr int QN = BOXW / VEC;                        // chunks per staged (row, plane)
@@ -467,45 +475,75 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
   const bool live = ix < N && iz < N;                   // ragged tiles: no store, but keep barriers
   const double c = 0.5 * (N - 1);
   const double rx = ix - c, rz = iz - c;
-  const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
   const int rowoff = (M - N) / 2;
-  const size_t plane_sz = size_t(K) * M;                // values per detector row of the stack
+  const size_t view_sz = size_t(K) * M * M;             // values per view of the stack
   const bool vec = (M % VEC) == 0;
-  const double ax = tx0 - c, bx = tx0 + GT - 1 - c, az = tz0 - c, bz = tz0 + GT - 1 - c;
 
-  // box origin of view n from the tile corners (uniform over the workgroup)
+  // Box origins: lane l of every wave computes the origin of view obase + l (FP64, from
+  // the tile corners); per view the workgroup-uniform origin is read out of lane n - obase
+  // into scalar registers, so the per-view cost is two lane reads.
+  const int lane = threadIdx.x & 63;
+  int obase = -64, lane_c0 = 0, lane_p0 = 0;
   auto origin = [&](int n, int& c0, int& p0) {
-    const ViewGeom& g = geom[n];
-    const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
-    const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
-    c0 = int(floor(cmin)) & ~(VEC - 1);                 // 16-byte aligned column start
-    p0 = flat ? 0 : int(floor(pmin));
+    if (n >= obase + 64) {                              // uniform: every 64 views
+      obase = n;
+      const int v = n + lane;
+      int cc = 0, pp = 0;
+      if (v < nb) {
+        const int t0 = opaque(tx0), z0 = opaque(tz0);
+        const double ax = t0 - c, bx = t0 + GT - 1 - c, az = z0 - c, bz = z0 + GT - 1 - c;
+        const ViewGeom& g = geom[v];
+        const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
+        const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
+        cc = int(floor(cmin)) & ~(VEC - 1);             // 16-byte aligned column start
+        pp = flat ? 0 : int(floor(pmin));
+      }
+      lane_c0 = cc;
+      lane_p0 = pp;
+    }
+    c0 = __builtin_amdgcn_readlane(lane_c0, n - obase);
+    p0 = __builtin_amdgcn_readlane(lane_p0, n - obase);
   };
-  // this thread's share of view n's box, into registers.  Every load reads a clamped,
-  // in-bounds address (no divergent zero-initialisation, so the loads stay in flight);
-  // slots outside the stack are marked in `valid` and zeroed when staged.
-  // The view-independent part of every staged chunk, computed once: its (plane, column)
-  // position in the box, the clamped detector-row term of its address, and its LDS offset.
-  // Per view only the box origin moves, so the fetch is a few integer ops per chunk.
+  // Per staged chunk, computed once: its (plane, column) position in the box, the
+  // detector-row term of its address, its LDS offset, and its byte offset from the box
+  // origin when every row exists.  Boxes that lie wholly inside the stack (the common case)
+  // are fetched with one buffer load per chunk (the per-view origin is the scalar offset)
+  // and staged without masks; boxes that cross the stack's edge take a clamped, masked path.
+  // every row of the block exists and lies on the detector
+  const bool rows_in = y0 + YB <= N && y0 + rowoff >= 0 && y0 + YB - 1 + rowoff < M;
+  const bool small = view_sz * sizeof(InT) <= size_t(0x7fffffff);   // buffer offsets are 32-bit
   int cq[PER], cpl[PER], crow[PER], cdst[PER];
+  unsigned cfo[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = threadIdx.x + 256 * i;
     const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
     const int row = y0 + j + rowoff;
-    const bool rok = e < NE && (y0 + j < N) && unsigned(row) < unsigned(M);
     cq[i] = VEC * q;
     cpl[i] = pl;
-    crow[i] = rok ? row * K : -1;
+    crow[i] = (e < NE && y0 + j < N && unsigned(row) < unsigned(M)) ? row * K : -1;
     cdst[i] = e < NE ? (j * AX_BOXH + pl) * BOXP + VEC * q : -1;
+    cfo[i] = (e < NE && rows_in) ? unsigned((row * K + pl) * M + VEC * q) * unsigned(sizeof(InT)) : 0u;
   }
-  // this thread's share of view n's box, into registers.  Every load reads a clamped,
-  // in-bounds address (no divergent zero-initialisation, so the loads stay in flight);
-  // slots outside the stack are marked in `valid` and zeroed when staged.
-  auto fetch = [&](int n, int c0, int p0, uint4 (&v)[PER], unsigned& valid) {
-    const InT* vbase = stack + size_t(n) * plane_sz * M;
+  // this thread's share of view n's box, into registers.  Every load reads an in-bounds
+  // address (clamped where the box crosses the stack's edge, with the slots outside marked
+  // in `valid` and zeroed when staged; no divergent zero-initialisation, so the loads stay
+  // in flight).  Returns whether the box lies wholly inside the stack (uniform).
+  auto fetch = [&](int n, int c0, int p0, uint4 (&v)[PER], unsigned& valid) -> bool {
+    const InT* vbase = stack + size_t(n) * view_sz;
     valid = 0u;
     if (vec) {
+      if (rows_in && small && p0 >= 0 && p0 + AX_BOXH <= K && c0 >= 0 && c0 + BOXW <= M) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<InT*>(vbase), short(0), int(view_sz * sizeof(InT)), 0x00020000);
+        const int so = (p0 * M + c0) * int(sizeof(InT));
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const auto r = __builtin_amdgcn_raw_buffer_load_b128(rs, int(cfo[i]), so, 0);
+          v[i] = make_uint4(r[0], r[1], r[2], r[3]);
+        }
+        return true;
+      }
       // M and the column starts are multiples of VEC: a chunk lies wholly inside or outside a row
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
@@ -516,11 +554,11 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
                              unsigned(min(max(cc, 0), M - VEC));
         v[i] = *reinterpret_cast<const uint4*>(vbase + off);
       }
-      return;
+      return false;
     }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + 256 * i;
+      const int e = opaque(threadIdx.x + 256 * i);
       const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
       const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + VEC * q;
       const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
@@ -538,19 +576,34 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
       if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K))
         valid |= (1u << i);                              // partial chunks carry their own zeros
     }
+    return false;
   };
-  auto stage = [&](const uint4 (&v)[PER], unsigned valid) {
-    float* boxf = &box[0][0][0];
+  auto put = [&](int i, const Chunk16& x) {
+    float* dst = &box[0][0][0] + cdst[i];
+#pragma unroll
+    for (int h = 0; h < VEC; h += 4)
+      *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
+                                                        chunk_value<InT>(x, h + 2), chunk_value<InT>(x, h + 3));
+  };
+  auto stage = [&](const uint4 (&v)[PER], unsigned valid, bool inside) {
+    // chunks i < PER - 1 always exist (e < 256 (PER - 1) < NE)
+    if (inside) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (NE % 256 == 0 || i < PER - 1 || cdst[i] >= 0) {
+          Chunk16 x;
+          x.u = v[i];
+          put(i, x);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       if (cdst[i] >= 0) {
         Chunk16 x;
         x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
-        float* dst = boxf + cdst[i];
-#pragma unroll
-        for (int h = 0; h < VEC; h += 4)
-          *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
-                                                            chunk_value<InT>(x, h + 2), chunk_value<InT>(x, h + 3));
+        put(i, x);
       }
     }
   };
@@ -560,32 +613,38 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
   for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
   uint4 buf[PER];
   unsigned valid = 0u;
+  bool inside = false;
   int c0 = 0, p0 = 0;
   if (nb > 0) {
     origin(0, c0, p0);
-    fetch(0, c0, p0, buf, valid);
+    inside = fetch(0, c0, p0, buf, valid);
   }
   for (int n = 0; n < nb; ++n) {
     __syncthreads();                                    // previous view's LDS reads are done
-    stage(buf, valid);
+    stage(buf, valid, inside);
     __syncthreads();
     const int cc0 = c0, pp0 = p0;
     if (n + 1 < nb) {                                   // next view's loads overlap this view's math
       origin(n + 1, c0, p0);
-      fetch(n + 1, c0, p0, buf, valid);
+      inside = fetch(n + 1, c0, p0, buf, valid);
     }
     if (live) {
       const ViewGeom& g = geom[n];
-      const float inv = scale ? 1.0f / scale[n] : 1.0f;  // exact: the scale is a power of two
       // box-local coordinates; fmax guards against a rounding-level dip below the box origin
-      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + hm - cc0, 0.0);
-      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + hk - pp0, 0.0);
+      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + (hm - cc0), 0.0);
+      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + (hk - pp0), 0.0);
       const double fc0 = floor(fc), fp0 = floor(fp);
-      const float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
+      float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
       const int lc = int(fc0), lp = flat ? 0 : int(fp0);
       // taps lie inside the staged box by construction (0 <= lc, lc+1 < BOXW; same for planes)
-      const float w00 = (1.0f - tz) * (1.0f - tx) * inv, w01 = (1.0f - tz) * tx * inv;
-      const float w10 = tz * (1.0f - tx) * inv, w11 = tz * tx * inv;
+      float ux = 1.0f - tx;
+      if constexpr (std::is_same<InT, __half>::value) {
+        const float inv = 1.0f / scale[n];              // exact: the scale is a power of two
+        ux *= inv;
+        tx *= inv;
+      }
+      const float w00 = (1.0f - tz) * ux, w01 = (1.0f - tz) * tx;
+      const float w10 = tz * ux, w11 = tz * tx;
       const int lp1 = flat ? lp : lp + 1;
 #pragma unroll
       for (int j = 0; j < YB; ++j) {
@@ -594,6 +653,164 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
         acc[j] += w00 * r0[0] + w01 * r0[1] + w10 * r1[0] + w11 * r1[1];
       }
     }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int j = 0; j < YB; ++j) {
+    const int iy = y0 + j;
+    if (iy < N) {
+      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
+      *dst = accumulate ? *dst + acc[j] : acc[j];
+    }
+  }
+}
+
+// FP32 single-axis gridding with the footprints fetched straight into LDS.  The staged box
+// of k_grid_axis is chunk-linear (7 16-byte chunks per (row, plane), no padding), so wave w's
+// i-th load of a view covers chunks 256 i + 64 w + lane, and buffer loads with the LDS
+// destination write them in place (lane l's 16 bytes land 16 l bytes after the wave's LDS
+// base; lanes past the last chunk are switched off and write nothing).  Chunks outside the
+// stack get an offset beyond the buffer's range, which the hardware fills with zeros, so no
+// masks or register staging are needed.  Two box buffers alternate: view n + 1 is in flight
+// while view n is interpolated, and each view takes one barrier.
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr unsigned kOutOfRange = 0x80000000u;      // beyond every buffer range: reads as zero
+
+template <int YB>
+__global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__ stack,
+                                                       const ViewGeom* __restrict__ geom,
+                                                       float* __restrict__ vol, int N, int M, int K, int nb,
+                                                       int accumulate, int flat, double hm, double hk) {
+  constexpr int VEC = 4, BOXW = 28, BOXP = 28, QN = BOXW / VEC;
+  constexpr int NE = YB * AX_BOXH * QN;                 // chunks per staged view
+  constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
+  __shared__ __attribute__((aligned(16))) float box0[NE * VEC];
+  __shared__ __attribute__((aligned(16))) float box1[NE * VEC];
+  const int ntx = (N + GT - 1) / GT;
+  const int tiles = ntx * ntx;
+  const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
+  const int yblk = xcd + 8 * (k / tiles), tile = k % tiles;
+  const int y0 = yblk * YB;
+  if (y0 >= N) return;                                  // uniform
+  const int tx0 = (tile % ntx) * GT, tz0 = (tile / ntx) * GT;
+  const int ix = tx0 + (threadIdx.x % GT);
+  const int iz = tz0 + (threadIdx.x / GT);
+  const bool live = ix < N && iz < N;
+  const double c = 0.5 * (N - 1);
+  const double rx = ix - c, rz = iz - c;
+  const int rowoff = (M - N) / 2;
+  const size_t view_sz = size_t(K) * M * M;
+  const int wbase = (threadIdx.x & ~63) * VEC;          // this wave's first float in a box, per load
+  const int lane = threadIdx.x & 63;
+
+  // box origins, one view per lane (as in k_grid_axis)
+  int obase = -64, lane_c0 = 0, lane_p0 = 0;
+  auto origin = [&](int n, int& c0, int& p0) {
+    if (n >= obase + 64) {
+      obase = n;
+      const int v = n + lane;
+      int cc = 0, pp = 0;
+      if (v < nb) {
+        const int t0 = opaque(tx0), z0 = opaque(tz0);
+        const double ax = t0 - c, bx = t0 + GT - 1 - c, az = z0 - c, bz = z0 + GT - 1 - c;
+        const ViewGeom& g = geom[v];
+        const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
+        const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
+        cc = int(floor(cmin)) & ~(VEC - 1);
+        pp = flat ? 0 : int(floor(pmin));
+      }
+      lane_c0 = cc;
+      lane_p0 = pp;
+    }
+    c0 = __builtin_amdgcn_readlane(lane_c0, n - obase);
+    p0 = __builtin_amdgcn_readlane(lane_p0, n - obase);
+  };
+  // per chunk slot: byte offset from the box origin (rows all present), and for boxes that
+  // cross the stack's edge its (plane, column) position and detector-row term
+  // (the host launches this kernel only for M a multiple of 4 and views below 2^31 bytes)
+  const bool rows_in = y0 + YB <= N && y0 + rowoff >= 0 && y0 + YB - 1 + rowoff < M;
+  unsigned cfo[PER];
+  int cq[PER], cpl[PER], crow[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
+    const int row = y0 + j + rowoff;
+    cq[i] = VEC * q;
+    cpl[i] = pl;
+    crow[i] = (e < NE && y0 + j < N && unsigned(row) < unsigned(M)) ? row * K : -1;
+    cfo[i] = rows_in ? unsigned((row * K + pl) * M + VEC * q) * 4u : kOutOfRange;
+  }
+  // slot i exists for every thread below the last load; in the last one only below NE
+  auto has = [&](int i) { return NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE; };
+  auto load = [&](int n, int c0, int p0, float* dst) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(stack + size_t(n) * view_sz), short(0), int(view_sz * sizeof(float)), 0x00020000);
+    if (rows_in && p0 >= 0 && p0 + AX_BOXH <= K && c0 >= 0 && c0 + BOXW <= M) {
+      const int so = (p0 * M + c0) * 4;
+#pragma unroll
+      for (int i = 0; i < PER; ++i)
+        if (has(i))
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 256 * VEC * i + wbase), 16,
+                                                   int(cfo[i]), so, 0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (has(i)) {
+          const int pp = p0 + cpl[i], cc = c0 + cq[i];
+          const bool ok = crow[i] >= 0 && unsigned(pp) < unsigned(K) && unsigned(cc) < unsigned(M);
+          const unsigned off = ok ? unsigned((crow[i] + pp) * M + cc) * 4u : kOutOfRange;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 256 * VEC * i + wbase), 16, int(off),
+                                                   0, 0, 0);
+        }
+      }
+    }
+  };
+
+  float acc[YB];
+#pragma unroll
+  for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
+  int oc0 = 0, op0 = 0, oc1 = 0, op1 = 0;              // origins of the views in each buffer
+  // view n from buffer b: wait for this wave's loads of it (and for its own reads of the
+  // other buffer), barrier (every wave's share has landed; every wave is done with the
+  // other buffer), issue view n + 1 into the other buffer, interpolate
+  auto step = [&](float* bx, int& cb, int& pb, float* other, int& co, int& po, int n) {
+    if (n >= nb) return;                                // uniform
+    __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
+    // a plain barrier: the workgroup fence of __syncthreads is not needed after the wait
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (n + 1 < nb) {
+      origin(n + 1, co, po);
+      load(n + 1, co, po, other);
+    }
+    if (live) {
+      const ViewGeom& g = geom[n];
+      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + (hm - cb), 0.0);
+      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + (hk - pb), 0.0);
+      const double fc0 = floor(fc), fp0 = floor(fp);
+      const float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
+      const int lc = int(fc0), lp = flat ? 0 : int(fp0);
+      const float ux = 1.0f - tx;
+      const float w00 = (1.0f - tz) * ux, w01 = (1.0f - tz) * tx;
+      const float w10 = tz * ux, w11 = tz * tx;
+      const int lp1 = flat ? lp : lp + 1;
+#pragma unroll
+      for (int j = 0; j < YB; ++j) {
+        const float* r0 = bx + (j * AX_BOXH + lp) * BOXP + lc;
+        const float* r1 = bx + (j * AX_BOXH + lp1) * BOXP + lc;
+        acc[j] += w00 * r0[0] + w01 * r0[1] + w10 * r1[0] + w11 * r1[1];
+      }
+    }
+  };
+  if (nb > 0) {
+    origin(0, oc0, op0);
+    load(0, oc0, op0, box0);
+  }
+  for (int n0 = 0; n0 < nb; n0 += 2) {
+    step(box0, oc0, op0, box1, oc1, op1, n0);
+    step(box1, oc1, op1, box0, oc0, op0, n0 + 1);
   }
   if (!live) return;
 #pragma unroll
@@ -1242,12 +1459,21 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
                             float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
   const InT* st = static_cast<const InT*>(stack);
+  if constexpr (std::is_same<InT, float>::value) {
+    if (axis_fast && M % 4 == 0 && size_t(K) * M * M * sizeof(float) <= size_t(0x7fffffff)) {
+      const int tiles = int(grid.x * grid.y);
+      const int yblocks8 = int((grid.z + 7) / 8 * 8);
+      hipLaunchKernelGGL((k_grid_axis_dma<kYB>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
+                         vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
+      return hipGetLastError();
+    }
+  }
   if (axis_fast) {
     // flat grid: (x, z) tiles x row blocks, row blocks padded to a multiple of 8 (one XCD each)
     const int tiles = int(grid.x * grid.y);
     const int yblocks8 = int((grid.z + 7) / 8 * 8);
     hipLaunchKernelGGL((k_grid_axis<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
-                       scale, vol, N, M, K, nb, accumulate, flat);
+                       scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
   } else {
     const int tiles = int(grid.x * grid.y);
     const int yblocks8 = int((grid.z + 7) / 8 * 8);
