@@ -665,27 +665,42 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
   }
 }
 
-// FP32 single-axis gridding with the footprints fetched straight into LDS.  The staged box
-// of k_grid_axis is chunk-linear (7 16-byte chunks per (row, plane), no padding), so wave w's
+// Single-axis gridding of FP32 or BF16 planes with the footprints fetched straight into LDS
+// in their storage type.  The staged box is chunk-linear (16-byte chunks, 7 per (row, plane)
+// for FP32, 4 for BF16; no padding), so wave w's
 // i-th load of a view covers chunks 256 i + 64 w + lane, and buffer loads with the LDS
 // destination write them in place (lane l's 16 bytes land 16 l bytes after the wave's LDS
 // base; lanes past the last chunk are switched off and write nothing).  Chunks outside the
 // stack get an offset beyond the buffer's range, which the hardware fills with zeros, so no
 // masks or register staging are needed.  Two box buffers alternate: view n + 1 is in flight
-// while view n is interpolated, and each view takes one barrier.
+// while view n is interpolated, and each view takes one barrier.  A BF16 tap pair (lc, lc + 1)
+// is the 32-bit window at bit 16 (lc & 1) of the two dwords from element 2 (lc >> 1).
+template <class InT>
+struct DmaBox;
+template <>
+struct DmaBox<float> {
+  static constexpr int VEC = 4, BOXW = 28;
+};
+template <>
+struct DmaBox<__hip_bfloat16> {
+  static constexpr int VEC = 8, BOXW = 32;
+};
 typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr unsigned kOutOfRange = 0x80000000u;      // beyond every buffer range: reads as zero
 
-template <int YB>
-__global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__ stack,
+template <int YB, class InT>
+__global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ stack,
                                                        const ViewGeom* __restrict__ geom,
                                                        float* __restrict__ vol, int N, int M, int K, int nb,
                                                        int accumulate, int flat, double hm, double hk) {
-  constexpr int VEC = 4, BOXW = 28, BOXP = 28, QN = BOXW / VEC;
+  constexpr int VEC = DmaBox<InT>::VEC, BOXW = DmaBox<InT>::BOXW, QN = BOXW / VEC;
+  constexpr int ES = int(sizeof(InT));                  // bytes per stored value
+  constexpr int PITCH = BOXW * ES / 4;                  // dwords per staged (row, plane)
   constexpr int NE = YB * AX_BOXH * QN;                 // chunks per staged view
   constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
-  __shared__ __attribute__((aligned(16))) float box0[NE * VEC];
-  __shared__ __attribute__((aligned(16))) float box1[NE * VEC];
+  // one dword of padding: the BF16 pair read may touch the dword after a row's last
+  __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + 4];
+  __shared__ __attribute__((aligned(16))) unsigned box1[NE * 4 + 4];
   const int ntx = (N + GT - 1) / GT;
   const int tiles = ntx * ntx;
   const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
@@ -700,7 +715,7 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__
   const double rx = ix - c, rz = iz - c;
   const int rowoff = (M - N) / 2;
   const size_t view_sz = size_t(K) * M * M;
-  const int wbase = (threadIdx.x & ~63) * VEC;          // this wave's first float in a box, per load
+  const int wbase = (threadIdx.x & ~63) * 4;            // this wave's first dword in a box, per load
   const int lane = threadIdx.x & 63;
 
   // box origins, one view per lane (as in k_grid_axis)
@@ -739,19 +754,19 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__
     cq[i] = VEC * q;
     cpl[i] = pl;
     crow[i] = (e < NE && y0 + j < N && unsigned(row) < unsigned(M)) ? row * K : -1;
-    cfo[i] = rows_in ? unsigned((row * K + pl) * M + VEC * q) * 4u : kOutOfRange;
+    cfo[i] = rows_in ? unsigned((row * K + pl) * M + VEC * q) * unsigned(ES) : kOutOfRange;
   }
   // slot i exists for every thread below the last load; in the last one only below NE
   auto has = [&](int i) { return NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE; };
-  auto load = [&](int n, int c0, int p0, float* dst) {
+  auto load = [&](int n, int c0, int p0, unsigned* dst) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(stack + size_t(n) * view_sz), short(0), int(view_sz * sizeof(float)), 0x00020000);
+        const_cast<InT*>(stack + size_t(n) * view_sz), short(0), int(view_sz * ES), 0x00020000);
     if (rows_in && p0 >= 0 && p0 + AX_BOXH <= K && c0 >= 0 && c0 + BOXW <= M) {
-      const int so = (p0 * M + c0) * 4;
+      const int so = (p0 * M + c0) * ES;
 #pragma unroll
       for (int i = 0; i < PER; ++i)
         if (has(i))
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 256 * VEC * i + wbase), 16,
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 1024 * i + wbase), 16,
                                                    int(cfo[i]), so, 0, 0);
     } else {
 #pragma unroll
@@ -759,9 +774,9 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__
         if (has(i)) {
           const int pp = p0 + cpl[i], cc = c0 + cq[i];
           const bool ok = crow[i] >= 0 && unsigned(pp) < unsigned(K) && unsigned(cc) < unsigned(M);
-          const unsigned off = ok ? unsigned((crow[i] + pp) * M + cc) * 4u : kOutOfRange;
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 256 * VEC * i + wbase), 16, int(off),
-                                                   0, 0, 0);
+          const unsigned off = ok ? unsigned((crow[i] + pp) * M + cc) * unsigned(ES) : kOutOfRange;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 1024 * i + wbase), 16, int(off), 0,
+                                                   0, 0);
         }
       }
     }
@@ -774,7 +789,7 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__
   // view n from buffer b: wait for this wave's loads of it (and for its own reads of the
   // other buffer), barrier (every wave's share has landed; every wave is done with the
   // other buffer), issue view n + 1 into the other buffer, interpolate
-  auto step = [&](float* bx, int& cb, int& pb, float* other, int& co, int& po, int n) {
+  auto step = [&](unsigned* bx, int& cb, int& pb, unsigned* other, int& co, int& po, int n) {
     if (n >= nb) return;                                // uniform
     __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
     // a plain barrier: the workgroup fence of __syncthreads is not needed after the wait
@@ -798,9 +813,21 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const float* __restrict__
       const int lp1 = flat ? lp : lp + 1;
 #pragma unroll
       for (int j = 0; j < YB; ++j) {
-        const float* r0 = bx + (j * AX_BOXH + lp) * BOXP + lc;
-        const float* r1 = bx + (j * AX_BOXH + lp1) * BOXP + lc;
-        acc[j] += w00 * r0[0] + w01 * r0[1] + w10 * r1[0] + w11 * r1[1];
+        float a0, a1, b0, b1;                           // taps (lp, lc), (lp, lc+1), (lp1, lc), (lp1, lc+1)
+        if constexpr (ES == 4) {
+          const float* r0 = reinterpret_cast<const float*>(bx) + (j * AX_BOXH + lp) * PITCH + lc;
+          const float* r1 = reinterpret_cast<const float*>(bx) + (j * AX_BOXH + lp1) * PITCH + lc;
+          a0 = r0[0], a1 = r0[1], b0 = r1[0], b1 = r1[1];
+        } else {
+          const unsigned* r0 = bx + (j * AX_BOXH + lp) * PITCH + (lc >> 1);
+          const unsigned* r1 = bx + (j * AX_BOXH + lp1) * PITCH + (lc >> 1);
+          const unsigned sh = unsigned(lc & 1) * 16u;
+          const unsigned pa = __builtin_amdgcn_alignbit(r0[1], r0[0], sh);
+          const unsigned pb2 = __builtin_amdgcn_alignbit(r1[1], r1[0], sh);
+          a0 = __uint_as_float(pa << 16), a1 = __uint_as_float(pa & 0xffff0000u);
+          b0 = __uint_as_float(pb2 << 16), b1 = __uint_as_float(pb2 & 0xffff0000u);
+        }
+        acc[j] += w00 * a0 + w01 * a1 + w10 * b0 + w11 * b1;
       }
     }
   };
@@ -1459,11 +1486,11 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
                             float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
   const InT* st = static_cast<const InT*>(stack);
-  if constexpr (std::is_same<InT, float>::value) {
-    if (axis_fast && M % 4 == 0 && size_t(K) * M * M * sizeof(float) <= size_t(0x7fffffff)) {
+  if constexpr (std::is_same<InT, float>::value || std::is_same<InT, __hip_bfloat16>::value) {
+    if (axis_fast && M % DmaBox<InT>::VEC == 0 && size_t(K) * M * M * sizeof(InT) <= size_t(0x7fffffff)) {
       const int tiles = int(grid.x * grid.y);
       const int yblocks8 = int((grid.z + 7) / 8 * 8);
-      hipLaunchKernelGGL((k_grid_axis_dma<kYB>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
+      hipLaunchKernelGGL((k_grid_axis_dma<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
                          vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
       return hipGetLastError();
     }
