@@ -98,6 +98,14 @@ def make(name: str) -> Problem:
         lam, sig = 0.3e-10, 0.2
         imgs = _born(16, N, M, dx, lam, dirs, dist, sig, count=6)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
+    if name == "narrow48":
+        # detector narrower than the volume (M < N): voxel rows beyond the detector get nothing
+        n, N, M, K = 9, 48, 32, 48
+        dirs = scan.single_axis(n, 180.0, offset_deg=5.0)
+        dist = np.full(n, 40e-10)
+        lam, sig = 0.1e-10, 0.1
+        imgs = _born(25, N, M, dx, lam, dirs, dist, sig, count=24)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
     if name == "m80":
         n, N, M, K = 4, 80, 80, 80
         dirs = scan.single_axis(n, 180.0)
@@ -165,4 +173,4 @@ def make(name: str) -> Problem:
 
 
 SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32",
-         "m256", "m256sph", "m160", "m192"]
+         "m256", "m256sph", "m160", "m192", "narrow48"]

@@ -24,7 +24,7 @@ def _rel(a, b):
     return float(np.linalg.norm((np.asarray(a) - b).ravel()) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("name", ["axis32", "sphere45", "ragged44", "pct64", "m256", "m256sph", "m160", "m192"])
+@pytest.mark.parametrize("name", ["axis32", "sphere45", "ragged44", "pct64", "m256", "m256sph", "m160", "m192", "narrow48"])
 @pytest.mark.parametrize("dtype", [1, 2], ids=["bf16", "fp16"])
 def test_mixed_precision_error_bounded(name, dtype):
     from paper_2206_09151_amd import tomo

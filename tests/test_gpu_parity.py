@@ -75,7 +75,7 @@ def test_plane_stacks_match_oracle(dev, name):
         assert _rel(got[i], ref) < TOL, (i, _rel(got[i], ref))
 
 
-@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16"])
+@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "narrow48"])
 def test_grid_of_oracle_planes_matches_oracle_gather(dev, name):
     """Gridding alone: the oracle's FP64 planes, rounded to FP32, gridded by both sides."""
     pb = _problems.make(name)
