@@ -80,10 +80,15 @@ def copy_probe(mib: int):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code: // comments, trailing blanks and empty lines are
+    left out, so that editing a comment does not orphan the stored counter summaries."""
     h = hashlib.sha256()
     for f in ("fft.hpp", "geom.hpp", "tomo_kernels.hip", "fourier_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_2206_09151_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2206_09151_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

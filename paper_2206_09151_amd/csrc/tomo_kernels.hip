@@ -406,7 +406,10 @@ constexpr int GT = 16;  // voxel tile edge (x) x (z or y) per 256-thread workgro
 // tile; the column start is rounded down to a 16-byte boundary) is staged into LDS as
 // FP32 for the YB rows with 16-byte loads, zero outside the stack, so the bilinear taps
 // are plain LDS reads with no bounds masks.  The next view's box is loaded into
-// registers while the current view is interpolated.
+// registers while the current view is interpolated.  (FP32 and BF16 planes take
+// k_grid_axis_dma below, which fetches the same box straight into LDS; this kernel
+// serves FP16 planes, whose values are rescaled when staged, and sizes that kernel
+// does not take.)
 template <class InT>
 struct AxisBox;
 template <>
