@@ -61,3 +61,19 @@ def test_mixed_precision_stage_entry_points(dtype):
         plan.grid(st, first, nb, acc)
     torch.cuda.synchronize()
     assert torch.equal(acc, full)
+
+
+@pytest.mark.parametrize("name", ["sphere45", "m192", "sampling32", "vaxes32"])
+@pytest.mark.parametrize("dtype", [1, 2], ids=["bf16", "fp16"])
+def test_cubic_tile_gridding_16bit(name, dtype):
+    """The cubic-tile gridding kernel (tune = 2) over general frames with 16-bit stacks."""
+    from paper_2206_09151_amd import tomo
+    pb = _problems.make(name)
+    plan = tomo.Plan(pb.params(tune=2, plane_dtype=dtype), pb.dirs, pb.dist, vaxes=pb.vaxes)
+    assert plan.grid_rows == 0
+    v = torch.empty((pb.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+    plan.reconstruct(torch.from_numpy(pb.images).to("cuda:0"), v)
+    ref = oracle.reconstruct(pb.images.astype(np.float64), pb.dirs, pb.dist, pb.oracle_geometry(), vaxes=pb.vaxes)
+    e16 = _rel(v.cpu().numpy().astype(np.float64), ref)
+    print(f"cubic tiles {name} dtype={dtype}: rel-L2 vs FP64 = {e16:.3e}")
+    assert e16 < BOUND[dtype], e16
