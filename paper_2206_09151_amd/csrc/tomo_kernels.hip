@@ -406,10 +406,9 @@ constexpr int GT = 16;  // voxel tile edge (x) x (z or y) per 256-thread workgro
 // tile; the column start is rounded down to a 16-byte boundary) is staged into LDS as
 // FP32 for the YB rows with 16-byte loads, zero outside the stack, so the bilinear taps
 // are plain LDS reads with no bounds masks.  The next view's box is loaded into
-// registers while the current view is interpolated.  (FP32 and BF16 planes take
-// k_grid_axis_dma below, which fetches the same box straight into LDS; this kernel
-// serves FP16 planes, whose values are rescaled when staged, and sizes that kernel
-// does not take.)
+// registers while the current view is interpolated.  (k_grid_axis_dma below fetches the
+// same box straight into LDS and serves every size whose views stay below 2^31 bytes; this
+// kernel takes the rest.)
 template <class InT>
 struct AxisBox;
 template <>
@@ -668,16 +667,17 @@ __global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack
   }
 }
 
-// Single-axis gridding of FP32 or BF16 planes with the footprints fetched straight into LDS
-// in their storage type.  The staged box is chunk-linear (16-byte chunks, 7 per (row, plane)
-// for FP32, 4 for BF16; no padding), so wave w's
+// Single-axis gridding of FP32, BF16 or FP16 planes with the footprints fetched straight into
+// LDS in their storage type.  The staged box is chunk-linear (16-byte chunks, 7 per (row,
+// plane) for FP32, 4 for 16-bit values; no padding), so wave w's
 // i-th load of a view covers chunks 256 i + 64 w + lane, and buffer loads with the LDS
 // destination write them in place (lane l's 16 bytes land 16 l bytes after the wave's LDS
 // base; lanes past the last chunk are switched off and write nothing).  Chunks outside the
 // stack get an offset beyond the buffer's range, which the hardware fills with zeros, so no
 // masks or register staging are needed.  Two box buffers alternate: view n + 1 is in flight
-// while view n is interpolated, and each view takes one barrier.  A BF16 tap pair (lc, lc + 1)
-// is the 32-bit window at bit 16 (lc & 1) of the two dwords from element 2 (lc >> 1).
+// while view n is interpolated, and each view takes one barrier.  A 16-bit tap pair (lc, lc + 1)
+// is the 32-bit window at bit 16 (lc & 1) of the two dwords from element 2 (lc >> 1); FP16
+// values are unscaled through the interpolation weights (the per-view scale is a power of two).
 template <class InT>
 struct DmaBox;
 template <>
@@ -688,12 +688,17 @@ template <>
 struct DmaBox<__hip_bfloat16> {
   static constexpr int VEC = 8, BOXW = 32;
 };
+template <>
+struct DmaBox<__half> {
+  static constexpr int VEC = 8, BOXW = 32;
+};
 typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr unsigned kOutOfRange = 0x80000000u;      // beyond every buffer range: reads as zero
 
 template <int YB, class InT>
 __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ stack,
                                                        const ViewGeom* __restrict__ geom,
+                                                       const float* __restrict__ scale,
                                                        float* __restrict__ vol, int N, int M, int K, int nb,
                                                        int accumulate, int flat, double hm, double hk) {
   constexpr int VEC = DmaBox<InT>::VEC, BOXW = DmaBox<InT>::BOXW, QN = BOXW / VEC;
@@ -808,9 +813,15 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
       const double fc = fmax(g.u[0] * rx + g.u[2] * rz + (hm - cb), 0.0);
       const double fp = fmax(g.d[0] * rx + g.d[2] * rz + (hk - pb), 0.0);
       const double fc0 = floor(fc), fp0 = floor(fp);
-      const float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
+      float tx = float(fc - fc0);
+      const float tz = flat ? 0.0f : float(fp - fp0);
       const int lc = int(fc0), lp = flat ? 0 : int(fp0);
-      const float ux = 1.0f - tx;
+      float ux = 1.0f - tx;
+      if constexpr (std::is_same<InT, __half>::value) {
+        const float inv = 1.0f / scale[n];              // exact: the scale is a power of two
+        ux *= inv;
+        tx *= inv;
+      }
       const float w00 = (1.0f - tz) * ux, w01 = (1.0f - tz) * tx;
       const float w10 = tz * ux, w11 = tz * tx;
       const int lp1 = flat ? lp : lp + 1;
@@ -827,8 +838,15 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
           const unsigned sh = unsigned(lc & 1) * 16u;
           const unsigned pa = __builtin_amdgcn_alignbit(r0[1], r0[0], sh);
           const unsigned pb2 = __builtin_amdgcn_alignbit(r1[1], r1[0], sh);
-          a0 = __uint_as_float(pa << 16), a1 = __uint_as_float(pa & 0xffff0000u);
-          b0 = __uint_as_float(pb2 << 16), b1 = __uint_as_float(pb2 & 0xffff0000u);
+          if constexpr (std::is_same<InT, __half>::value) {
+            a0 = __half2float(__ushort_as_half((unsigned short)(pa & 0xffffu)));
+            a1 = __half2float(__ushort_as_half((unsigned short)(pa >> 16)));
+            b0 = __half2float(__ushort_as_half((unsigned short)(pb2 & 0xffffu)));
+            b1 = __half2float(__ushort_as_half((unsigned short)(pb2 >> 16)));
+          } else {
+            a0 = __uint_as_float(pa << 16), a1 = __uint_as_float(pa & 0xffff0000u);
+            b0 = __uint_as_float(pb2 << 16), b1 = __uint_as_float(pb2 & 0xffff0000u);
+          }
         }
         acc[j] += w00 * a0 + w01 * a1 + w10 * b0 + w11 * b1;
       }
@@ -1489,12 +1507,12 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
                             float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
   const InT* st = static_cast<const InT*>(stack);
-  if constexpr (std::is_same<InT, float>::value || std::is_same<InT, __hip_bfloat16>::value) {
+  {
     if (axis_fast && M % DmaBox<InT>::VEC == 0 && size_t(K) * M * M * sizeof(InT) <= size_t(0x7fffffff)) {
       const int tiles = int(grid.x * grid.y);
       const int yblocks8 = int((grid.z + 7) / 8 * 8);
       hipLaunchKernelGGL((k_grid_axis_dma<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
-                         vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
+                         scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
       return hipGetLastError();
     }
   }
