@@ -706,9 +706,10 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
   constexpr int PITCH = BOXW * ES / 4;                  // dwords per staged (row, plane)
   constexpr int NE = YB * AX_BOXH * QN;                 // chunks per staged view
   constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
-  // one dword of padding: the BF16 pair read may touch the dword after a row's last
-  __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + 4];
-  __shared__ __attribute__((aligned(16))) unsigned box1[NE * 4 + 4];
+  // 16-bit values: one dword of padding, the pair read may touch the dword after a row's last
+  constexpr int PAD = ES == 2 ? 4 : 0;
+  __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + PAD];
+  __shared__ __attribute__((aligned(16))) unsigned box1[NE * 4 + PAD];
   const int ntx = (N + GT - 1) / GT;
   const int tiles = ntx * ntx;
   const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
