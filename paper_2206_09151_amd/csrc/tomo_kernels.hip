@@ -1236,69 +1236,6 @@ __global__ __launch_bounds__(256) void k_grid_cube(const InT* __restrict__ stack
   }
 }
 
-// General view frames: full trilinear interpolation per voxel.  Each thread owns
-// voxel column (ix, iy) and ZB consecutive iz.
-template <int ZB, class InT>
-__global__ __launch_bounds__(256) void k_grid_gen(const InT* __restrict__ stack,
-                                                  const ViewGeom* __restrict__ geom,
-                                                  const float* __restrict__ scale,
-                                                  float* __restrict__ vol, int N, int M, int K, int nb,
-                                                  int accumulate, int flat) {
-  const int ix = blockIdx.x * GT + (threadIdx.x % GT);
-  const int iy = blockIdx.y * GT + (threadIdx.x / GT);
-  const int z0 = blockIdx.z * ZB;
-  if (ix >= N || iy >= N) return;
-  const double c = 0.5 * (N - 1);
-  const double rx = ix - c, ry = iy - c;
-  const double hm = 0.5 * (M - 1), hk = 0.5 * (K - 1);
-  const size_t view_sz = size_t(M) * K * M;
-  float acc[ZB];
-#pragma unroll
-  for (int j = 0; j < ZB; ++j) acc[j] = 0.0f;
-  for (int n = 0; n < nb; ++n) {
-    const ViewGeom& g = geom[n];
-    const InT* base = stack + size_t(n) * view_sz;
-    const float inv = scale ? 1.0f / scale[n] : 1.0f;   // exact: the scale is a power of two
-    const double bc = g.u[0] * rx + g.u[1] * ry + hm;
-    const double br = g.v[0] * rx + g.v[1] * ry + hm;
-    const double bp = g.d[0] * rx + g.d[1] * ry + hk;
-#pragma unroll
-    for (int j = 0; j < ZB; ++j) {
-      const double rz = (z0 + j) - c;
-      const double fc = g.u[2] * rz + bc, fr = g.v[2] * rz + br, fp = g.d[2] * rz + bp;
-      const double fc0 = floor(fc), fr0 = floor(fr), fp0 = floor(fp);
-      const float tc = float(fc - fc0), tr = float(fr - fr0), tp = float(fp - fp0);
-      const int c0 = int(fc0), r0 = int(fr0), p0 = int(fp0);
-      const float wc0 = (unsigned(c0) < unsigned(M)) ? 1.0f - tc : 0.0f;
-      const float wc1 = (unsigned(c0 + 1) < unsigned(M)) ? tc : 0.0f;
-      const float wr0 = (unsigned(r0) < unsigned(M)) ? 1.0f - tr : 0.0f;
-      const float wr1 = (unsigned(r0 + 1) < unsigned(M)) ? tr : 0.0f;
-      const float wp0 = flat ? 1.0f : (unsigned(p0) < unsigned(K)) ? 1.0f - tp : 0.0f;
-      const float wp1 = flat ? 0.0f : (unsigned(p0 + 1) < unsigned(K)) ? tp : 0.0f;
-      const int c0c = min(max(c0, 0), M - 1), c1c = min(max(c0 + 1, 0), M - 1);
-      const int r0c = min(max(r0, 0), M - 1), r1c = min(max(r0 + 1, 0), M - 1);
-      const int p0c = min(max(p0, 0), K - 1), p1c = min(max(p0 + 1, 0), K - 1);
-      const InT* a0 = base + (size_t(r0c) * K + p0c) * M;
-      const InT* a1 = base + (size_t(r0c) * K + p1c) * M;
-      const InT* b0 = base + (size_t(r1c) * K + p0c) * M;
-      const InT* b1 = base + (size_t(r1c) * K + p1c) * M;
-      const float v0 = wc0 * from_store<InT>(a0[c0c]) + wc1 * from_store<InT>(a0[c1c]);
-      const float v1 = wc0 * from_store<InT>(a1[c0c]) + wc1 * from_store<InT>(a1[c1c]);
-      const float v2 = wc0 * from_store<InT>(b0[c0c]) + wc1 * from_store<InT>(b0[c1c]);
-      const float v3 = wc0 * from_store<InT>(b1[c0c]) + wc1 * from_store<InT>(b1[c1c]);
-      acc[j] += inv * (wr0 * (wp0 * v0 + wp1 * v1) + wr1 * (wp0 * v2 + wp1 * v3));
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < ZB; ++j) {
-    const int iz = z0 + j;
-    if (iz < N) {
-      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
-      *dst = accumulate ? *dst + acc[j] : acc[j];
-    }
-  }
-}
-
 // ------------------------------------------------------------------ plan tables (FP64)
 
 __device__ __forceinline__ double2 filter_value(const FilterArgs& fa, const ViewGeom& g,
