@@ -148,6 +148,14 @@ tomo_status tomo_grid(tomo_plan_t plan, const void* d_planes, int32_t first, int
  * the end to report TOMO_EDOMAIN. */
 tomo_status tomo_reconstruct(tomo_plan_t plan, const float* d_images, float* d_volume, void* stream);
 
+/* tomo_reconstruct without the final synchronisation: every kernel of the reconstruction
+ * is enqueued on the stream and the call returns at once, so that repeated
+ * reconstructions keep the GPU busy without a host round trip per call.  The result is
+ * the same as tomo_reconstruct's, bit for bit.  An invalid image value is reported as
+ * TOMO_EDOMAIN by the next tomo_sync (or tomo_reconstruct) on the plan; argument errors
+ * are returned at once as TOMO_EINVAL. */
+tomo_status tomo_reconstruct_async(tomo_plan_t plan, const float* d_images, float* d_volume, void* stream);
+
 /* Synchronise the stream and report any device-detected domain error since the
  * last report (TOMO_EDOMAIN) or TOMO_OK. */
 tomo_status tomo_sync(tomo_plan_t plan, void* stream);

@@ -691,6 +691,13 @@ tomo_status tomo_reconstruct(tomo_plan_t pl, const float* d_images, float* d_vol
   return tomo_sync(pl, stream);
 }
 
+tomo_status tomo_reconstruct_async(tomo_plan_t pl, const float* d_images, float* d_volume, void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (!d_images || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
+  return enqueue_reconstruct(pl, d_images, d_volume, static_cast<hipStream_t>(stream));
+}
+
 tomo_status tomo_timing_enable(tomo_plan_t pl, int32_t enable) {
   if (!pl) return TOMO_EINVAL;
   pl->timing = enable != 0;

@@ -25,7 +25,7 @@ F32, BF16, F16 = 0, 1, 2
 _MODES = {"ramp_axis": RAMP_AXIS, "ramp_iso": RAMP_ISO, "sampling": SAMPLING}
 
 EXPORTED = [
-    "tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_sync",
+    "tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_reconstruct_async", "tomo_sync",
     "tomo_filtered_spectra", "tomo_workspace_bytes", "tomo_batch_capacity", "tomo_stack_bytes",
     "tomo_status_string", "tomo_last_error", "tomo_plan_error", "tomo_destroy",
     "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_entries",
@@ -65,6 +65,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_backpropagate.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.tomo_grid.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.tomo_reconstruct.argtypes = [vp, vp, vp, vp]
+    lib.tomo_reconstruct_async.argtypes = [vp, vp, vp, vp]
     lib.tomo_sync.argtypes = [vp, vp]
     lib.tomo_filtered_spectra.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.tomo_workspace_bytes.argtypes = [ctypes.POINTER(TomoParams)]
@@ -95,7 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_batch_destroy.argtypes = [vp]
     for name in ("tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_destroy"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_sync",
+    for name in ("tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_reconstruct_async", "tomo_sync",
                  "tomo_filtered_spectra", "tomo_destroy", "tomo_batch_capacity", "tomo_timing_enable",
                  "tomo_timing_read", "tomo_fourier_reconstruct"):
         getattr(lib, name).restype = ctypes.c_int
@@ -221,6 +222,11 @@ class Plan:
     def reconstruct(self, images, volume, stream=None):
         self._check(_LIB.tomo_reconstruct(self._h, _dptr(images), _dptr(volume),
                                           ctypes.c_void_p(_stream_ptr(stream))))
+
+    def reconstruct_async(self, images, volume, stream=None):
+        """Enqueue a whole reconstruction without waiting; domain errors surface at sync()."""
+        self._check(_LIB.tomo_reconstruct_async(self._h, _dptr(images), _dptr(volume),
+                                                ctypes.c_void_p(_stream_ptr(stream))))
 
     def sync(self, stream=None):
         self._check(_LIB.tomo_sync(self._h, ctypes.c_void_p(_stream_ptr(stream))))

@@ -109,6 +109,7 @@ def test_plan_workspace_limit_gives_enomem():
 def test_null_plan_calls_are_rejected():
     lib = tomo.lib()
     assert lib.tomo_reconstruct(None, None, None, None) == tomo.EINVAL
+    assert lib.tomo_reconstruct_async(None, None, None, None) == tomo.EINVAL
     assert lib.tomo_grid(None, None, 0, 1, None, None) == tomo.EINVAL
     assert lib.tomo_backpropagate(None, None, 0, 1, None, None) == tomo.EINVAL
     assert lib.tomo_destroy(None) == tomo.OK

@@ -162,6 +162,37 @@ def test_domain_error_reported_and_cleared(dev):
     plan.reconstruct(torch.from_numpy(pb.images).to(dev), vol)   # flag was cleared
 
 
+@pytest.mark.parametrize("name", ["axis32", "sphere45"])
+def test_async_reconstruct_equals_reconstruct(dev, name):
+    """Enqueued reconstructions (no per-call synchronisation) give the synchronous result bit
+    for bit, also when several are in flight on the stream before one sync."""
+    pb = _problems.make(name)
+    plan = _plan(pb, angle_batch=5)
+    img = torch.from_numpy(pb.images).to(dev)
+    ref = torch.empty((pb.n_vox,) * 3, dtype=torch.float32, device=dev)
+    plan.reconstruct(img, ref)
+    out = torch.full_like(ref, float("nan"))
+    for _ in range(3):
+        plan.reconstruct_async(img, out)
+    plan.sync()
+    assert torch.equal(out, ref)
+
+
+def test_async_reconstruct_reports_domain_error_at_sync(dev):
+    tomo = _tomo()
+    pb = _problems.make("oddk16")
+    plan = _plan(pb)
+    bad = pb.images.copy()
+    bad[0, 5, 5] = -1.0
+    vol = torch.empty((pb.n_vox,) * 3, dtype=torch.float32, device=dev)
+    plan.reconstruct_async(torch.from_numpy(bad).to(dev), vol)   # returns without waiting
+    with pytest.raises(tomo.TomoError) as e:
+        plan.sync()
+    assert e.value.status == tomo.EDOMAIN
+    plan.reconstruct_async(torch.from_numpy(pb.images).to(dev), vol)
+    plan.sync()                                                   # flag was cleared
+
+
 def test_range_errors(dev):
     tomo = _tomo()
     pb = _problems.make("oddk16")
