@@ -216,7 +216,9 @@ hipEvent_t take_event(tomo_plan_s* pl) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing only (read after the stream is synchronised): no system-scope fence, which would
+  // write back and invalidate caches around every timed launch and slow the launches it times
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -545,7 +547,8 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       return cleanup_fail(err, "gridding autotune");
     };
     const size_t n3 = size_t(r.N) * r.N * r.N;
-    if ((e = dev_alloc(&d_vol, n3)) || (e = hipEventCreate(&ea)) || (e = hipEventCreate(&eb)) ||
+    if ((e = dev_alloc(&d_vol, n3)) || (e = hipEventCreateWithFlags(&ea, hipEventDisableSystemFence)) ||
+        (e = hipEventCreateWithFlags(&eb, hipEventDisableSystemFence)) ||
         (e = hipMemsetAsync(pl->d_stack, 0, size_t(r.batch) * stack_view_bytes(r.M, r.K, p->plane_dtype), s)) ||
         (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(pl->d_scale), 0x3f800000u, size_t(r.n), s)))
       return tune_fail(e);
