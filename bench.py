@@ -5,10 +5,11 @@
 
 One step = one full reconstruction (all views: contrast, DFT, eq. 11 filter,
 propagation to every depth plane, inverse FFTs, trilinear gridding) of the
-workload, images already resident in HBM, enqueued with tomo_reconstruct_async;
-the K timed steps end with one tomo_sync (domain errors of any step are still
-reported).  The time per step with a synchronisation after every call
-(tomo_reconstruct) is reported as ms_per_step_sync_each.  Prints one JSON line.  With
+workload, images already resident in HBM, enqueued with tomo_reconstruct_async
+(tomo_fourier_reconstruct_async for --method fourier); the K timed steps end with
+one tomo_sync (domain errors of any step are still reported).  The time per step
+with a synchronisation after every call is reported as ms_per_step_sync_each.
+Prints one JSON line.  With
 --method fourier a step is one reconstruction by the Fourier-space form instead
 (spectra, 3D gridding of the filtered spectra, normalisation, inverse 3D FFT);
 its throughput is quoted in the same unit (voxel*angle updates of the volume).
@@ -182,18 +183,18 @@ def main():
     batch = plan.batch
     fourier = args.method == "fourier"
 
-    # A real-space step is enqueued without a host round trip (tomo_reconstruct_async); the K
-    # steps end with one tomo_sync, which still reports a domain error of any of them.  The
-    # rate with a synchronisation after every call (tomo_reconstruct) is reported beside.
+    # A step is enqueued without a host round trip (tomo_reconstruct_async or
+    # tomo_fourier_reconstruct_async); the K steps end with one tomo_sync, which still reports
+    # a domain error of any of them.  The rate with a synchronisation after every call is
+    # reported beside.
     def step():
         if fourier:
-            plan.fourier_reconstruct(d_img, vol, variant=args.variant, nsr=args.nsr, stream=stream)
+            plan.fourier_reconstruct_async(d_img, vol, variant=args.variant, nsr=args.nsr, stream=stream)
         else:
             plan.reconstruct_async(d_img, vol, stream=stream)
 
     def finish():
-        if not fourier:
-            plan.sync(stream)
+        plan.sync(stream)
 
     for _ in range(args.warmup):
         step()
@@ -206,14 +207,15 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     ms = elapsed * 1e3 / args.steps
-    ms_sync_each = None
-    if not fourier:
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        if fourier:
+            plan.fourier_reconstruct(d_img, vol, variant=args.variant, nsr=args.nsr, stream=stream)
+        else:
             plan.reconstruct(d_img, vol, stream=stream)
-        torch.cuda.synchronize()
-        ms_sync_each = (time.perf_counter() - t) * 1e3 / args.steps
+    torch.cuda.synchronize()
+    ms_sync_each = (time.perf_counter() - t) * 1e3 / args.steps
     updates = float(w.n_vox) ** 3 * w.n_views
     value = updates / (ms * 1e-3)
     print(f"[bench] {ms:.3f} ms/step, {value:.4g} updates/s (batch {batch})", file=sys.stderr, flush=True)

@@ -190,6 +190,12 @@ typedef enum { TOMO_EQ11 = 11, TOMO_EQ12 = 12 } tomo_fourier_variant;
 tomo_status tomo_fourier_reconstruct(tomo_plan_t plan, const float* d_images, int32_t variant,
                                      double nsr, float* d_volume, void* stream);
 
+/* tomo_fourier_reconstruct without the final synchronisation (as tomo_reconstruct_async
+ * is to tomo_reconstruct): the kernels are enqueued and the call returns; a domain error
+ * is reported by the next tomo_sync; the result is the same bit for bit. */
+tomo_status tomo_fourier_reconstruct_async(tomo_plan_t plan, const float* d_images, int32_t variant,
+                                           double nsr, float* d_volume, void* stream);
+
 /* Per-kernel timing (tracing).  While enabled, every kernel launch of the plan is
  * bracketed by two HIP events recorded on the launch's stream.  Kinds:
  *   0 = contrast + DFT + filter (spectra), 1 = depth planes (inverse FFTs),

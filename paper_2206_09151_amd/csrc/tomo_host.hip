@@ -747,8 +747,9 @@ tomo_status tomo_filtered_spectra(tomo_plan_t pl, const float* d_images, int32_t
   return TOMO_OK;
 }
 
-tomo_status tomo_fourier_reconstruct(tomo_plan_t pl, const float* d_images, int32_t variant, double nsr,
-                                     float* d_volume, void* stream) {
+// Every kernel of one Fourier-space reconstruction, enqueued on the stream (no synchronisation).
+static tomo_status enqueue_fourier(tomo_plan_t pl, const float* d_images, int32_t variant, double nsr,
+                                   float* d_volume, void* stream) {
   if (!pl) return TOMO_EINVAL;
   pl->err.clear();
   if (!d_images || !d_volume) return fail(pl, TOMO_EINVAL, "null device pointer");
@@ -812,7 +813,19 @@ tomo_status tomo_fourier_reconstruct(tomo_plan_t pl, const float* d_images, int3
   }
   e = timed(pl, 4, s, [&] { return tomo::launch_fourier_fft3(pl->N, pl->d_fgrid, pl->d_tw3, d_volume, s); });
   if (e != hipSuccess) return dev_fail(pl, e, "Fourier inverse FFT kernels");
+  return TOMO_OK;
+}
+
+tomo_status tomo_fourier_reconstruct(tomo_plan_t pl, const float* d_images, int32_t variant, double nsr,
+                                     float* d_volume, void* stream) {
+  const tomo_status st = enqueue_fourier(pl, d_images, variant, nsr, d_volume, stream);
+  if (st != TOMO_OK) return st;
   return tomo_sync(pl, stream);
+}
+
+tomo_status tomo_fourier_reconstruct_async(tomo_plan_t pl, const float* d_images, int32_t variant, double nsr,
+                                           float* d_volume, void* stream) {
+  return enqueue_fourier(pl, d_images, variant, nsr, d_volume, stream);
 }
 
 // ---------------------------------------------------------------- batched jobs

@@ -28,7 +28,8 @@ EXPORTED = [
     "tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_reconstruct_async", "tomo_sync",
     "tomo_filtered_spectra", "tomo_workspace_bytes", "tomo_batch_capacity", "tomo_stack_bytes",
     "tomo_status_string", "tomo_last_error", "tomo_plan_error", "tomo_destroy",
-    "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_entries",
+    "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_reconstruct_async",
+    "tomo_fourier_entries",
     "tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_error", "tomo_batch_destroy",
     "tomo_grid_rows",
 ]
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_timing_enable.argtypes = [vp, i32]
     lib.tomo_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.tomo_fourier_reconstruct.argtypes = [vp, vp, i32, ctypes.c_double, vp, vp]
+    lib.tomo_fourier_reconstruct_async.argtypes = [vp, vp, i32, ctypes.c_double, vp, vp]
     lib.tomo_grid_rows.argtypes = [vp]
     lib.tomo_grid_rows.restype = i32
     lib.tomo_fourier_entries.argtypes = [vp]
@@ -98,7 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).restype = ctypes.c_int
     for name in ("tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_reconstruct_async", "tomo_sync",
                  "tomo_filtered_spectra", "tomo_destroy", "tomo_batch_capacity", "tomo_timing_enable",
-                 "tomo_timing_read", "tomo_fourier_reconstruct"):
+                 "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_reconstruct_async"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -239,6 +241,11 @@ class Plan:
         """The Fourier-space form (eq. 11 or eq. 12 by 3D gridding, NSR filter)."""
         self._check(_LIB.tomo_fourier_reconstruct(self._h, _dptr(images), int(variant), float(nsr), _dptr(volume),
                                                   ctypes.c_void_p(_stream_ptr(stream))))
+
+    def fourier_reconstruct_async(self, images, volume, variant: int = EQ11, nsr: float = 0.0, stream=None):
+        """fourier_reconstruct enqueued without waiting; domain errors surface at sync()."""
+        self._check(_LIB.tomo_fourier_reconstruct_async(self._h, _dptr(images), int(variant), float(nsr),
+                                                        _dptr(volume), ctypes.c_void_p(_stream_ptr(stream))))
 
     def timing(self, enable: bool):
         self._check(_LIB.tomo_timing_enable(self._h, 1 if enable else 0))

@@ -133,6 +133,7 @@ def test_timing_kinds_match_header():
 
 def test_null_plan_fourier_call_is_rejected():
     assert tomo.lib().tomo_fourier_reconstruct(None, None, 11, 0.0, None, None) == tomo.EINVAL
+    assert tomo.lib().tomo_fourier_reconstruct_async(None, None, 11, 0.0, None, None) == tomo.EINVAL
     assert tomo.lib().tomo_fourier_entries(None) == 0
 
 

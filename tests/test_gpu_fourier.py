@@ -146,3 +146,18 @@ def test_fourier_errors():
     assert ei.value.status == tomo.EDOMAIN
     plain.destroy()
     plan.destroy()
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_fourier_async_equals_sync(mode):
+    """Enqueued Fourier-space reconstructions (several in flight, one sync) give the
+    synchronous result bit for bit."""
+    prob = _problems.make("axis32")
+    ref, plan = _run(prob, mode=mode)
+    dev = torch.device("cuda:0")
+    imgs = torch.from_numpy(prob.images).to(dev)
+    vol = torch.full((prob.n_vox,) * 3, float("nan"), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        plan.fourier_reconstruct_async(imgs, vol)
+    plan.sync()
+    assert np.array_equal(vol.cpu().numpy().astype(np.float64), ref)
