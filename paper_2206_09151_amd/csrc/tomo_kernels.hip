@@ -397,18 +397,8 @@ __global__ void k_spectra_out(const float4* __restrict__ q, float2* __restrict__
 // ------------------------------------------------------------------ K4: gridding
 constexpr int GT = 16;  // voxel tile edge (x) x (z or y) per 256-thread workgroup
 
-// Single-axis views (v = y exactly, M - N even): the detector row of voxel row iy is
-// iy + (M-N)/2 exactly, so the trilinear weights reduce to bilinear ones in
-// (plane, col), shared by the YB voxel rows of a thread.
-//
-// Per view, the workgroup's 16 x 16 (x, z) tile maps into a rotated square of the
-// (plane, col) grid.  Its bounding box (at most 24 planes x 24 columns for a 16 x 16
-// tile; the column start is rounded down to a 16-byte boundary) is staged into LDS as
-// FP32 for the YB rows with 16-byte loads, zero outside the stack, so the bilinear taps
-// are plain LDS reads with no bounds masks.  The next view's box is loaded into
-// registers while the current view is interpolated.  (k_grid_axis_dma below fetches the
-// same box straight into LDS and serves every size whose views stay below 2^31 bytes; this
-// kernel takes the rest.)
+// Box geometry shared by the LDS-staged gridding kernels: 16-byte chunks of VEC stored
+// values, BOXW columns per staged (row, plane), LDS pitch BOXP, AX_BOXH planes per row.
 template <class InT>
 struct AxisBox;
 template <>
@@ -451,224 +441,15 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-template <int YB, class InT>
-__global__ __launch_bounds__(256) void k_grid_axis(const InT* __restrict__ stack,
-                                                   const ViewGeom* __restrict__ geom,
-                                                   const float* __restrict__ scale,
-                                                   float* __restrict__ vol, int N, int M, int K,
-                                                   int nb, int accumulate, int flat, double hm, double hk) {
-  using B = AxisBox<InT>;
-  constexpr int VEC = B::VEC, BOXW = B::BOXW, BOXP = B::BOXP;
-  constexpr int QN = BOXW / VEC;                        // chunks per staged (row, plane)
-  constexpr int NE = YB * AX_BOXH * QN;                 // chunks per staged view
-  constexpr int PER = (NE + 255) / 256;                 // chunks per thread
-  __shared__ float box[YB][AX_BOXH][BOXP];
-  // Workgroups are dealt to the 8 XCDs round robin: give every tile of one voxel-row
-  // block to the same XCD, so each detector row of the stacks is fetched into one L2.
-  const int ntx = (N + GT - 1) / GT;
-  const int tiles = ntx * ntx;                          // (x, z) tiles per row block
-  const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
-  const int yblk = xcd + 8 * (k / tiles), tile = k % tiles;
-  const int y0 = yblk * YB;
-  if (y0 >= N) return;                                  // uniform: the whole workgroup leaves
-  const int tx0 = (tile % ntx) * GT, tz0 = (tile / ntx) * GT;
-  const int ix = tx0 + (threadIdx.x % GT);
-  const int iz = tz0 + (threadIdx.x / GT);
-  const bool live = ix < N && iz < N;                   // ragged tiles: no store, but keep barriers
-  const double c = 0.5 * (N - 1);
-  const double rx = ix - c, rz = iz - c;
-  const int rowoff = (M - N) / 2;
-  const size_t view_sz = size_t(K) * M * M;             // values per view of the stack
-  const bool vec = (M % VEC) == 0;
-
-  // Box origins: lane l of every wave computes the origin of view obase + l (FP64, from
-  // the tile corners); per view the workgroup-uniform origin is read out of lane n - obase
-  // into scalar registers, so the per-view cost is two lane reads.
-  const int lane = threadIdx.x & 63;
-  int obase = -64, lane_c0 = 0, lane_p0 = 0;
-  auto origin = [&](int n, int& c0, int& p0) {
-    if (n >= obase + 64) {                              // uniform: every 64 views
-      obase = n;
-      const int v = n + lane;
-      int cc = 0, pp = 0;
-      if (v < nb) {
-        const int t0 = opaque(tx0), z0 = opaque(tz0);
-        const double ax = t0 - c, bx = t0 + GT - 1 - c, az = z0 - c, bz = z0 + GT - 1 - c;
-        const ViewGeom& g = geom[v];
-        const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
-        const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
-        cc = int(floor(cmin)) & ~(VEC - 1);             // 16-byte aligned column start
-        pp = flat ? 0 : int(floor(pmin));
-      }
-      lane_c0 = cc;
-      lane_p0 = pp;
-    }
-    c0 = __builtin_amdgcn_readlane(lane_c0, n - obase);
-    p0 = __builtin_amdgcn_readlane(lane_p0, n - obase);
-  };
-  // Per staged chunk, computed once: its (plane, column) position in the box, the
-  // detector-row term of its address, its LDS offset, and its byte offset from the box
-  // origin when every row exists.  Boxes that lie wholly inside the stack (the common case)
-  // are fetched with one buffer load per chunk (the per-view origin is the scalar offset)
-  // and staged without masks; boxes that cross the stack's edge take a clamped, masked path.
-  // every row of the block exists and lies on the detector
-  const bool rows_in = y0 + YB <= N && y0 + rowoff >= 0 && y0 + YB - 1 + rowoff < M;
-  const bool small = view_sz * sizeof(InT) <= size_t(0x7fffffff);   // buffer offsets are 32-bit
-  int cq[PER], cpl[PER], crow[PER], cdst[PER];
-  unsigned cfo[PER];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
-    const int row = y0 + j + rowoff;
-    cq[i] = VEC * q;
-    cpl[i] = pl;
-    crow[i] = (e < NE && y0 + j < N && unsigned(row) < unsigned(M)) ? row * K : -1;
-    cdst[i] = e < NE ? (j * AX_BOXH + pl) * BOXP + VEC * q : -1;
-    cfo[i] = (e < NE && rows_in) ? unsigned((row * K + pl) * M + VEC * q) * unsigned(sizeof(InT)) : 0u;
-  }
-  // this thread's share of view n's box, into registers.  Every load reads an in-bounds
-  // address (clamped where the box crosses the stack's edge, with the slots outside marked
-  // in `valid` and zeroed when staged; no divergent zero-initialisation, so the loads stay
-  // in flight).  Returns whether the box lies wholly inside the stack (uniform).
-  auto fetch = [&](int n, int c0, int p0, uint4 (&v)[PER], unsigned& valid) -> bool {
-    const InT* vbase = stack + size_t(n) * view_sz;
-    valid = 0u;
-    if (vec) {
-      if (rows_in && small && p0 >= 0 && p0 + AX_BOXH <= K && c0 >= 0 && c0 + BOXW <= M) {
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<InT*>(vbase), short(0), int(view_sz * sizeof(InT)), 0x00020000);
-        const int so = (p0 * M + c0) * int(sizeof(InT));
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-          const auto r = __builtin_amdgcn_raw_buffer_load_b128(rs, int(cfo[i]), so, 0);
-          v[i] = make_uint4(r[0], r[1], r[2], r[3]);
-        }
-        return true;
-      }
-      // M and the column starts are multiples of VEC: a chunk lies wholly inside or outside a row
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int pp = p0 + cpl[i], cc = c0 + cq[i];
-        const bool ok = crow[i] >= 0 && unsigned(pp) < unsigned(K) && unsigned(cc) < unsigned(M);
-        valid |= ok ? (1u << i) : 0u;
-        const unsigned off = unsigned(max(crow[i], 0) + min(max(pp, 0), K - 1)) * unsigned(M) +
-                             unsigned(min(max(cc, 0), M - VEC));
-        v[i] = *reinterpret_cast<const uint4*>(vbase + off);
-      }
-      return false;
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = opaque(threadIdx.x + 256 * i);
-      const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
-      const int row = y0 + j + rowoff, pp = p0 + pl, cc = c0 + VEC * q;
-      const int rowc = min(max(row, 0), M - 1), ppc = min(max(pp, 0), K - 1);
-      const InT* src = vbase + (size_t(rowc) * K + ppc) * M;
-      Chunk16 x;
-#pragma unroll
-      for (int kk = 0; kk < VEC; ++kk) {
-        const int ce = min(max(cc + kk, 0), M - 1);
-        const float fv = from_store<InT>(src[ce]);
-        const bool ek = unsigned(cc + kk) < unsigned(M);
-        if constexpr (VEC == 4) x.f[kk] = ek ? fv : 0.0f;
-        else x.h[kk] = ek ? reinterpret_cast<const unsigned short*>(src)[ce] : (unsigned short)0;
-      }
-      v[i] = x.u;
-      if (e < NE && (y0 + j < N) && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K))
-        valid |= (1u << i);                              // partial chunks carry their own zeros
-    }
-    return false;
-  };
-  auto put = [&](int i, const Chunk16& x) {
-    float* dst = &box[0][0][0] + cdst[i];
-#pragma unroll
-    for (int h = 0; h < VEC; h += 4)
-      *reinterpret_cast<float4*>(dst + h) = make_float4(chunk_value<InT>(x, h), chunk_value<InT>(x, h + 1),
-                                                        chunk_value<InT>(x, h + 2), chunk_value<InT>(x, h + 3));
-  };
-  auto stage = [&](const uint4 (&v)[PER], unsigned valid, bool inside) {
-    // chunks i < PER - 1 always exist (e < 256 (PER - 1) < NE)
-    if (inside) {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        if (NE % 256 == 0 || i < PER - 1 || cdst[i] >= 0) {
-          Chunk16 x;
-          x.u = v[i];
-          put(i, x);
-        }
-      }
-      return;
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      if (cdst[i] >= 0) {
-        Chunk16 x;
-        x.u = (valid >> i) & 1u ? v[i] : make_uint4(0u, 0u, 0u, 0u);
-        put(i, x);
-      }
-    }
-  };
-
-  float acc[YB];
-#pragma unroll
-  for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
-  uint4 buf[PER];
-  unsigned valid = 0u;
-  bool inside = false;
-  int c0 = 0, p0 = 0;
-  if (nb > 0) {
-    origin(0, c0, p0);
-    inside = fetch(0, c0, p0, buf, valid);
-  }
-  for (int n = 0; n < nb; ++n) {
-    __syncthreads();                                    // previous view's LDS reads are done
-    stage(buf, valid, inside);
-    __syncthreads();
-    const int cc0 = c0, pp0 = p0;
-    if (n + 1 < nb) {                                   // next view's loads overlap this view's math
-      origin(n + 1, c0, p0);
-      inside = fetch(n + 1, c0, p0, buf, valid);
-    }
-    if (live) {
-      const ViewGeom& g = geom[n];
-      // box-local coordinates; fmax guards against a rounding-level dip below the box origin
-      const double fc = fmax(g.u[0] * rx + g.u[2] * rz + (hm - cc0), 0.0);
-      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + (hk - pp0), 0.0);
-      const double fc0 = floor(fc), fp0 = floor(fp);
-      float tx = float(fc - fc0), tz = flat ? 0.0f : float(fp - fp0);
-      const int lc = int(fc0), lp = flat ? 0 : int(fp0);
-      // taps lie inside the staged box by construction (0 <= lc, lc+1 < BOXW; same for planes)
-      float ux = 1.0f - tx;
-      if constexpr (std::is_same<InT, __half>::value) {
-        const float inv = 1.0f / scale[n];              // exact: the scale is a power of two
-        ux *= inv;
-        tx *= inv;
-      }
-      const float w00 = (1.0f - tz) * ux, w01 = (1.0f - tz) * tx;
-      const float w10 = tz * ux, w11 = tz * tx;
-      const int lp1 = flat ? lp : lp + 1;
-#pragma unroll
-      for (int j = 0; j < YB; ++j) {
-        const float* r0 = &box[j][lp][lc];
-        const float* r1 = &box[j][lp1][lc];
-        acc[j] += w00 * r0[0] + w01 * r0[1] + w10 * r1[0] + w11 * r1[1];
-      }
-    }
-  }
-  if (!live) return;
-#pragma unroll
-  for (int j = 0; j < YB; ++j) {
-    const int iy = y0 + j;
-    if (iy < N) {
-      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
-      *dst = accumulate ? *dst + acc[j] : acc[j];
-    }
-  }
-}
-
-// Single-axis gridding of FP32, BF16 or FP16 planes with the footprints fetched straight into
-// LDS in their storage type.  The staged box is chunk-linear (16-byte chunks, 7 per (row,
+// Single-axis views (v = y exactly, M - N even): the detector row of voxel row iy is
+// iy + (M-N)/2 exactly, so the trilinear weights reduce to bilinear ones in (plane, col),
+// shared by the YB voxel rows of a thread.  Per view, the workgroup's 16 x 16 (x, z) tile
+// maps into a rotated square of the (plane, col) grid; its bounding box (at most 24 planes x
+// 24 columns; the column start rounded down to a 16-byte boundary) is staged in LDS for the
+// YB rows, zero outside the stack, so the bilinear taps are plain LDS reads.
+//
+// The footprints of FP32, BF16 or FP16 planes are fetched straight into LDS in their
+// storage type.  The staged box is chunk-linear (16-byte chunks, 7 per (row,
 // plane) for FP32, 4 for 16-bit values; no padding), so wave w's
 // i-th load of a view covers chunks 256 i + 64 w + lane, and buffer loads with the LDS
 // destination write them in place (lane l's 16 bytes land 16 l bytes after the wave's LDS
@@ -727,7 +508,9 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
   const int wbase = (threadIdx.x & ~63) * 4;            // this wave's first dword in a box, per load
   const int lane = threadIdx.x & 63;
 
-  // box origins, one view per lane (as in k_grid_axis)
+  // Box origins: lane l of every wave computes the origin of view obase + l (FP64, from
+  // the tile corners); per view the workgroup-uniform origin is read out of lane n - obase
+  // into scalar registers, so the per-view cost is two lane reads.
   int obase = -64, lane_c0 = 0, lane_p0 = 0;
   auto origin = [&](int n, int& c0, int& p0) {
     if (n >= obase + 64) {
@@ -751,7 +534,7 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
   };
   // per chunk slot: byte offset from the box origin (rows all present), and for boxes that
   // cross the stack's edge its (plane, column) position and detector-row term
-  // (the host launches this kernel only for M a multiple of 4 and views below 2^31 bytes)
+  // (the host launches this kernel only for M a multiple of VEC and views below 2^31 bytes)
   const bool rows_in = y0 + YB <= N && y0 + rowoff >= 0 && y0 + YB - 1 + rowoff < M;
   unsigned cfo[PER];
   int cq[PER], cpl[PER], crow[PER];
@@ -1445,20 +1228,14 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
                             float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
   const dim3 grid((N + GT - 1) / GT, (N + GT - 1) / GT, (N + kYB - 1) / kYB);
   const InT* st = static_cast<const InT*>(stack);
-  {
-    if (axis_fast && M % DmaBox<InT>::VEC == 0 && size_t(K) * M * M * sizeof(InT) <= size_t(0x7fffffff)) {
-      const int tiles = int(grid.x * grid.y);
-      const int yblocks8 = int((grid.z + 7) / 8 * 8);
-      hipLaunchKernelGGL((k_grid_axis_dma<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
-                         scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
-      return hipGetLastError();
-    }
-  }
   if (axis_fast) {
-    // flat grid: (x, z) tiles x row blocks, row blocks padded to a multiple of 8 (one XCD each)
+    // flat grid: (x, z) tiles x row blocks, row blocks padded to a multiple of 8 (one XCD each).
+    // Supported sizes (M a multiple of 16, K <= 2 N <= 512) always meet the kernel's conditions.
+    if (M % DmaBox<InT>::VEC != 0 || size_t(K) * M * M * sizeof(InT) > size_t(0x7fffffff))
+      return hipErrorInvalidValue;
     const int tiles = int(grid.x * grid.y);
     const int yblocks8 = int((grid.z + 7) / 8 * 8);
-    hipLaunchKernelGGL((k_grid_axis<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
+    hipLaunchKernelGGL((k_grid_axis_dma<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
                        scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
   } else {
     const int tiles = int(grid.x * grid.y);
