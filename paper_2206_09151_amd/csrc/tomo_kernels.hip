@@ -594,12 +594,15 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
     }
     if (live) {
       const ViewGeom& g = geom[n];
+      // flat (one plane, K = 1): a zero depth direction gives fp = 0 (hk = 0, origin plane
+      // 0), so lp = 0 and tz = 0, and the second plane's taps (zero-filled) get weight 0
+      const double d0 = flat ? 0.0 : g.d[0], d2 = flat ? 0.0 : g.d[2];
       const double fc = fmax(g.u[0] * rx + g.u[2] * rz + (hm - cb), 0.0);
-      const double fp = fmax(g.d[0] * rx + g.d[2] * rz + (hk - pb), 0.0);
-      const double fc0 = floor(fc), fp0 = floor(fp);
-      float tx = float(fc - fc0);
-      const float tz = flat ? 0.0f : float(fp - fp0);
-      const int lc = int(fc0), lp = flat ? 0 : int(fp0);
+      const double fp = fmax(d0 * rx + d2 * rz + (hk - pb), 0.0);
+      // fc, fp >= 0: truncation is the floor, fract the remainder (exact in FP64)
+      const int lc = int(fc), lp = int(fp);
+      float tx = float(__builtin_amdgcn_fract(fc));
+      const float tz = float(__builtin_amdgcn_fract(fp));
       float ux = 1.0f - tx;
       if constexpr (std::is_same<InT, __half>::value) {
         const float inv = 1.0f / scale[n];              // exact: the scale is a power of two
@@ -608,17 +611,17 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
       }
       const float w00 = (1.0f - tz) * ux, w01 = (1.0f - tz) * tx;
       const float w10 = tz * ux, w11 = tz * tx;
-      const int lp1 = flat ? lp : lp + 1;
+      const int pofs = int(__umul24(unsigned(lp), unsigned(PITCH)));   // lp < AX_BOXH
 #pragma unroll
       for (int j = 0; j < YB; ++j) {
-        float a0, a1, b0, b1;                           // taps (lp, lc), (lp, lc+1), (lp1, lc), (lp1, lc+1)
+        float a0, a1, b0, b1;                           // taps (lp, lc), (lp, lc+1), (lp+1, lc), (lp+1, lc+1)
         if constexpr (ES == 4) {
-          const float* r0 = reinterpret_cast<const float*>(bx) + (j * AX_BOXH + lp) * PITCH + lc;
-          const float* r1 = reinterpret_cast<const float*>(bx) + (j * AX_BOXH + lp1) * PITCH + lc;
+          const float* r0 = reinterpret_cast<const float*>(bx) + j * AX_BOXH * PITCH + pofs + lc;
+          const float* r1 = r0 + PITCH;
           a0 = r0[0], a1 = r0[1], b0 = r1[0], b1 = r1[1];
         } else {
-          const unsigned* r0 = bx + (j * AX_BOXH + lp) * PITCH + (lc >> 1);
-          const unsigned* r1 = bx + (j * AX_BOXH + lp1) * PITCH + (lc >> 1);
+          const unsigned* r0 = bx + j * AX_BOXH * PITCH + pofs + (lc >> 1);
+          const unsigned* r1 = r0 + PITCH;
           const unsigned sh = unsigned(lc & 1) * 16u;
           const unsigned pa = __builtin_amdgcn_alignbit(r0[1], r0[0], sh);
           const unsigned pb2 = __builtin_amdgcn_alignbit(r1[1], r1[0], sh);
@@ -632,7 +635,7 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
             b0 = __uint_as_float(pb2 << 16), b1 = __uint_as_float(pb2 & 0xffff0000u);
           }
         }
-        acc[j] += w00 * a0 + w01 * a1 + w10 * b0 + w11 * b1;
+        acc[j] = fmaf(w11, b1, fmaf(w10, b0, fmaf(w01, a1, fmaf(w00, a0, acc[j]))));
       }
     }
   };
