@@ -70,9 +70,9 @@ __device__ __forceinline__ float2 rot(float2 v) {
   } else if constexpr (4 * k == 3 * R) {
     return qturn<!INV>(v);
   } else {
-    constexpr float c = float(ce_cos_turn(k, R));
-    constexpr float s = float(INV ? ce_sin_turn(k, R) : -ce_sin_turn(k, R));
-    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+      constexpr float c = float(ce_cos_turn(k, R));
+      constexpr float s = float(INV ? ce_sin_turn(k, R) : -ce_sin_turn(k, R));
+      return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
   }
 }
 
@@ -196,6 +196,7 @@ struct Fft2Shape {
   static constexpr int LDS_SPLIT_FLOATS = (M * TP > R1 * SPF) ? M * TP : R1 * SPF;
   static_assert(R1 * R2 == M && R1 % R2 == 0, "M = R1*R2 with R2 | R1");
   static_assert(T <= 1024, "at most 1024 threads");
+  static_assert(R1 * (R2 * M + 4) <= LDS_SPLIT_FLOATS, "paired exchange fits the split buffer");
 };
 
 // Twiddle table tw[k] = exp(sgn i 2 pi k / M), FP64-rounded; index (r*s) mod M.
@@ -292,22 +293,47 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
 #pragma unroll
   for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
   // ---- exchange 1: x[s] of (line, r) -> thread (line, sgc) gets x[e*R2 + rr] = X1[s = sgc*E + e][rr]
+  if constexpr (E % 2 == 0) {
+    // the values of stage-1 outputs s and s+1 side by side (s even): each thread writes and
+    // reads 8 bytes at a time, half the LDS instructions for the same bytes
+    float2* lds2 = reinterpret_cast<float2*>(lds);
+    constexpr int SP2 = R2 * M + 4;
 #pragma unroll
-  for (int comp = 0; comp < 2; ++comp) {
+    for (int comp = 0; comp < 2; ++comp) {
 #pragma unroll
-    for (int s = 0; s < R1; ++s) lds[s * SPF + r * M + line] = comp ? x[s].y : x[s].x;
-    __syncthreads();
+      for (int s = 0; s < R1; s += 2)
+        lds2[(s / 2) * SP2 + r * M + line] = comp ? make_float2(x[s].y, x[s + 1].y) : make_float2(x[s].x, x[s + 1].x);
+      __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int s = sgc * E + e;
+      for (int e = 0; e < E; e += 2) {
+        const int i = (sgc * E + e) / 2;
 #pragma unroll
-      for (int rr = 0; rr < R2; ++rr) {
-        const float v = lds[s * SPF + rr * M + line];
-        if (comp) x[e * R2 + rr].y = v;
-        else x[e * R2 + rr].x = v;
+        for (int rr = 0; rr < R2; ++rr) {
+          const float2 v = lds2[i * SP2 + rr * M + line];
+          if (comp) { x[e * R2 + rr].y = v.x; x[(e + 1) * R2 + rr].y = v.y; }
+          else { x[e * R2 + rr].x = v.x; x[(e + 1) * R2 + rr].x = v.y; }
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+      for (int s = 0; s < R1; ++s) lds[s * SPF + r * M + line] = comp ? x[s].y : x[s].x;
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int s = sgc * E + e;
+#pragma unroll
+        for (int rr = 0; rr < R2; ++rr) {
+          const float v = lds[s * SPF + rr * M + line];
+          if (comp) x[e * R2 + rr].y = v;
+          else x[e * R2 + rr].x = v;
+        }
+      }
+      __syncthreads();
+    }
   }
   // ---- column pass, stage 2 (radix R2 over rr), in place per e
 #pragma unroll
@@ -336,22 +362,45 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
   for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
   // ---- exchange 3: thread (sg = t % R2, y = t / R2) gets X1[s = sg*E + e][rr] of row y
   const int sg = t % R2, yy = t / R2;
+  if constexpr (E % 2 == 0) {
+    float2* lds2 = reinterpret_cast<float2*>(lds);
+    constexpr int SP2 = R2 * M + 4;
 #pragma unroll
-  for (int comp = 0; comp < 2; ++comp) {
+    for (int comp = 0; comp < 2; ++comp) {
 #pragma unroll
-    for (int s = 0; s < R1; ++s) lds[s * SPF + r * M + line] = comp ? x[s].y : x[s].x;
-    __syncthreads();
+      for (int s = 0; s < R1; s += 2)
+        lds2[(s / 2) * SP2 + r * M + line] = comp ? make_float2(x[s].y, x[s + 1].y) : make_float2(x[s].x, x[s + 1].x);
+      __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int s = sg * E + e;
+      for (int e = 0; e < E; e += 2) {
+        const int i = (sg * E + e) / 2;
 #pragma unroll
-      for (int rr = 0; rr < R2; ++rr) {
-        const float v = lds[s * SPF + rr * M + yy];
-        if (comp) x[e * R2 + rr].y = v;
-        else x[e * R2 + rr].x = v;
+        for (int rr = 0; rr < R2; ++rr) {
+          const float2 v = lds2[i * SP2 + rr * M + yy];
+          if (comp) { x[e * R2 + rr].y = v.x; x[(e + 1) * R2 + rr].y = v.y; }
+          else { x[e * R2 + rr].x = v.x; x[(e + 1) * R2 + rr].x = v.y; }
+        }
       }
+      if (comp == 0) __syncthreads();
     }
-    if (comp == 0) __syncthreads();
+  } else {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+      for (int s = 0; s < R1; ++s) lds[s * SPF + r * M + line] = comp ? x[s].y : x[s].x;
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int s = sg * E + e;
+#pragma unroll
+        for (int rr = 0; rr < R2; ++rr) {
+          const float v = lds[s * SPF + rr * M + yy];
+          if (comp) x[e * R2 + rr].y = v;
+          else x[e * R2 + rr].x = v;
+        }
+      }
+      if (comp == 0) __syncthreads();
+    }
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) Dft<R2, INV>::run(&x[e * R2]);
