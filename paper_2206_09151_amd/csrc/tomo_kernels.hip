@@ -191,11 +191,19 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
     const float4 qq = qv[ky * M + line];
     x[m] = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
   }
+  // FP16 planes: per-view power-of-two scale (other storage types are not scaled), read
+  // before the transform so that its latency overlaps the spectrum loads; the empty asm
+  // keeps the compiler from sinking the read to the stores, where its wait would also
+  // wait for the last exchange's LDS reads
+  float sc = 1.0f;
+  if constexpr (std::is_same<OutT, __half>::value) {
+    sc = scale[view];
+    asm volatile("" : "+v"(sc));
+  }
   if constexpr (kSplit<M>) fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw_inv);
   else fft2_block<S, true>(x, lds, tw_inv);
   const int sg = t % S::R2, y = t / S::R2;
   const int pa = p, pb = K - 1 - p;
-  const float sc = scale ? scale[view] : 1.0f;
   OutT* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
   OutT* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
 #pragma unroll
@@ -365,11 +373,19 @@ __global__ __launch_bounds__(Shape<H>::T) void k_planes2x(const float4* __restri
     const int ti = p1 * n1 + p2 * n2;   // < 2H
     x[m] = cmul(acc, tw256[ti >= M ? ti - M : ti]);
   }
+  // FP16 planes: per-view power-of-two scale (other storage types are not scaled), read
+  // before the transform so that its latency overlaps the spectrum loads; the empty asm
+  // keeps the compiler from sinking the read to the stores, where its wait would also
+  // wait for the last exchange's LDS reads
+  float sc = 1.0f;
+  if constexpr (std::is_same<OutT, __half>::value) {
+    sc = scale[view];
+    asm volatile("" : "+v"(sc));
+  }
   fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw128);
   const int sg = t % S::R2, yy = t / S::R2;
   const int y = 2 * yy + p1;
   const int pa = p, pb = K - 1 - p;
-  const float sc = scale ? scale[view] : 1.0f;
   OutT* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
   OutT* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
 #pragma unroll
@@ -1159,7 +1175,7 @@ static hipError_t planes_dtype(int dtype, const float4* q, const float2* prop, c
   switch (dtype) {
     case 0: return planes_impl<M, float>(q, prop, tw, stack, K, npairs, nb, nullptr, s);
     case 1: return planes_impl<M, __hip_bfloat16>(q, prop, tw, stack, K, npairs, nb, nullptr, s);
-    case 2: return planes_impl<M, __half>(q, prop, tw, stack, K, npairs, nb, scale, s);
+    case 2: return scale ? planes_impl<M, __half>(q, prop, tw, stack, K, npairs, nb, scale, s) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -1211,7 +1227,8 @@ static hipError_t planes2x_dtype(int dtype, const float4* q, const float2* prop,
   switch (dtype) {
     case 0: return planes2x_impl<H, float>(q, prop, tw256, tw128, stack, K, npairs, nb, nullptr, s);
     case 1: return planes2x_impl<H, __hip_bfloat16>(q, prop, tw256, tw128, stack, K, npairs, nb, nullptr, s);
-    case 2: return planes2x_impl<H, __half>(q, prop, tw256, tw128, stack, K, npairs, nb, scale, s);
+    case 2: return scale ? planes2x_impl<H, __half>(q, prop, tw256, tw128, stack, K, npairs, nb, scale, s)
+                         : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
