@@ -169,9 +169,17 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
   __shared__ float2 lds[kSplit<M> ? (S::LDS_SPLIT_FLOATS + 1) / 2 : S::LDS_ELEMS];
   const int wg = blockIdx.x;
   const int xcd = wg & 7, k = wg >> 3;
-  const int view = xcd + 8 * (k / npairs);
-  const int p = k % npairs;
-  if (view >= nb) return;  // whole workgroup leaves together: no barrier is skipped by part of it
+  int view, p;
+  if (nb == 1 || nb == 2 || nb == 4) {
+    // fewer views than XCDs: view xcd % nb, its pairs dealt over the 8 / nb XCDs that share it
+    view = xcd % nb;
+    p = k * (8 / nb) + xcd / nb;
+    if (p >= npairs) return;  // whole workgroup leaves together: no barrier is skipped by part of it
+  } else {
+    view = xcd + 8 * (k / npairs);
+    p = k % npairs;
+    if (view >= nb) return;
+  }
   const int t = threadIdx.x;
   const int line = t % M;
   int r_;
@@ -1163,8 +1171,11 @@ static hipError_t spectra_impl(const float* images, const float4* filt, const fl
 template <int M, class OutT>
 static hipError_t planes_impl(const float4* q, const float2* prop, const float2* tw, void* stack, int K,
                               int npairs, int nb, const float* scale, hipStream_t s) {
-  const int nb8 = (nb + 7) / 8;
-  hipLaunchKernelGGL((k_planes<M, OutT>), dim3(8 * npairs * nb8), dim3(Shape<M>::T), 0, s, q, prop, tw,
+  // one workgroup per (view, pair), eight XCD columns; the kernel's mapping for nb = 1, 2, 4
+  // spreads each view's pairs over 8 / nb XCDs
+  const int reps = (nb == 1 || nb == 2 || nb == 4) ? 8 / nb : 0;
+  const int rows = reps ? (npairs + reps - 1) / reps : npairs * ((nb + 7) / 8);
+  hipLaunchKernelGGL((k_planes<M, OutT>), dim3(8 * rows), dim3(Shape<M>::T), 0, s, q, prop, tw,
                      static_cast<OutT*>(stack), K, npairs, nb, scale);
   return hipGetLastError();
 }
