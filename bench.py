@@ -150,8 +150,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "multi-GPU runs are not part of it", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (got --gpus {args.gpus}); "
+              "there is no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         run_batch(args)
