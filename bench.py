@@ -16,13 +16,15 @@ its throughput is quoted in the same unit (voxel*angle updates of the volume).
 
 The roofline object is computed for the kernel with the largest share of the
 step, from library-side HIP event timing (two events around every launch, on
-the launch's stream) over a second timed region of the same K steps: against
-the HBM peak with algorithmic bytes, except for the plane kernel, whose FFTs
-are bound by vector arithmetic: against the FP32 vector peak with algorithmic
-FLOPs (its HBM rate is reported beside).  The CPU
-baseline is the FP64 oracle on a bounded view subset of the same workload,
-timed on the host (rank 0, N=1 only); the same subset gives the rel-L2 of the
-GPU partial sum against the oracle over all N^3 voxels.
+the launch's stream) over a second timed region of the same K steps: its
+algorithmic HBM bytes per launch over its average launch duration, against the
+8 TB/s HBM peak.  Beside it: the whole step's algorithmic bytes against the same
+peak, and for the plane kernel its FFT arithmetic (5 n log2 n per complex 2D FFT of
+n = M^2 points, i.e. 2.5 log2(M^2) per voxel-angle update) against the FP32 vector
+peak.  The CPU baseline is the FP64 oracle on the host's cores (its views split over
+threads, partial sums added in order), over every view of the workload when that
+fits the CPU budget (else a view subset), in the same run (rank 0, N = 1 only); the
+same views give the rel-L2 of the GPU result against the oracle over all N^3 voxels.
 """
 from __future__ import annotations
 
@@ -38,8 +40,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BF16_MFMA_PEAK = 2500.0          # TFLOP/s, dense BF16 matrix cores
-FP32_VECTOR_PEAK = 157.3         # TFLOP/s, FP32 vector (256 CUs x 256 FLOP/clk x 2.4 GHz, packed)
-FP32_VALU_PEAK = 157.3e3       # GFLOP/s (packed FMA); plain lane ops: 256 CU * 64 lanes * 2.4 GHz
+FP32_VECTOR_PEAK = 157.3         # TFLOP/s, FP32 vector with packed FMA (256 CUs x 256 FLOP/clk x 2.4 GHz)
+FP32_UNPACKED_PEAK = 78.6        # TFLOP/s, FP32 vector without packed instructions (how this library is built)
+CPU_BUDGET_UPDATES = 4.0e8       # oracle sample: at most this many voxel-angle updates (all views of 128^3 x 180)
 
 
 def parse():
@@ -57,7 +60,9 @@ def parse():
                     help="storage type of the plane stacks (interpolation and sums stay FP32)")
     ap.add_argument("--cpu-voxels", type=int, default=0,
                     help="evaluate the oracle sample at this many seeded voxels (0: all voxels)")
-    ap.add_argument("--cpu-views", type=int, default=48, help="views in the oracle sample")
+    ap.add_argument("--cpu-views", type=int, default=0,
+                    help="views in the oracle sample (0: all views when N^3 n fits the CPU budget, else a subset)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="host threads of the oracle (0: all, at most 16)")
     ap.add_argument("--method", default="realspace", choices=["realspace", "fourier"])
     ap.add_argument("--variant", type=int, default=11, choices=[11, 12], help="Fourier-space form: eq. 11 or 12")
     ap.add_argument("--nsr", type=float, default=0.0, help="Fourier-space noise filter level (0: off)")
@@ -122,13 +127,58 @@ def algorithmic_bytes(kind: str, w, nb: int, first_batch: bool, sbytes: int = 4,
 
 
 def plane_flops(w, nb: int) -> float:
-    """Algorithmic FP32 operations of the plane kernel over nb views: per plane pair one
-    complex 2D FFT of M^2 points (5 n log2 n with n = M^2) and the spectrum of the pair
-    from Q1, Q2 and the separable propagator (12 per coefficient)."""
+    """Algorithmic FFT operations of the plane kernel over nb views: one complex 2D FFT of
+    n = M^2 points per plane pair, 5 n log2 n (the radix-2 count), i.e. 2.5 log2(M^2) per
+    voxel-angle update when K = M = N."""
     M = w.M
     npairs = (w.K + 1) // 2 if w.ewald else 1
     n = float(M) * M
-    return nb * npairs * (5.0 * n * np.log2(n) + 12.0 * n)
+    return nb * npairs * 5.0 * n * np.log2(n)
+
+
+def path_bytes_per_update(w, sbytes: int) -> float:
+    """Algorithmic HBM bytes of a whole reconstruction per voxel-angle update: per view the
+    image read and the plane stack written and read, plus the volume written once."""
+    per_view = 4.0 * w.M * w.M + 2.0 * sbytes * w.M * w.K * w.M
+    return (w.n_views * per_view + 4.0 * w.n_vox ** 3) / (float(w.n_vox) ** 3 * w.n_views)
+
+
+def host_threads(requested: int = 0) -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    n = max(1, min(16, n))
+    return min(requested, n) if requested > 0 else n
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threaded(images, dirs, dist, geo, views, threads: int, voxels=None):
+    """The oracle's sum over `views`, the views cut into contiguous chunks run in host
+    threads (numpy releases the interpreter lock in its array work; BLAS held to one
+    thread each), partial sums added in chunk order.  The oracle itself is unchanged."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    chunks = [c for c in np.array_split(np.asarray(views), min(threads, len(views))) if len(c)]
+    with threadpool_limits(1):
+        with ThreadPoolExecutor(len(chunks)) as ex:
+            parts = list(ex.map(lambda c: oracle.reconstruct_views(images, dirs, dist, geo, views=c,
+                                                                   voxels=voxels), chunks))
+    out = parts[0]
+    for p in parts[1:]:
+        out = out + p
+    return out
 
 
 def read_traffic(kind: str, src_hash: str, workload: str, storage: str):
@@ -257,26 +307,31 @@ def main():
         dom = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
         src_hash = kernel_source_hash()
         achieved = kernels[dom]["GBps"]
+        sb = 4 if args.plane_dtype == "f32" else 2
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": read_traffic(dom, src_hash, w.name, args.plane_dtype),
                     "ms_per_step_with_events": round(ms_timed, 4), "kernel_source_hash": src_hash}
-        if dom == "planes":
-            # the plane kernel is bound by the FFT's vector arithmetic, not by its HBM writes:
-            # report its FP32 rate against the vector peak, its HBM rate alongside
+        if not fourier:
+            pb = path_bytes_per_update(w, sb)
+            roofline["path"] = {"bytes_per_update": round(pb, 3), "achieved": round(pb * value / 1e9, 1),
+                                "frac": round(pb * value / 1e9 / HBM_PEAK_GBS, 4)}
+        if "planes" in kernels:
+            # the plane kernel's FFT arithmetic beside its bytes: it is bound by vector
+            # arithmetic and LDS exchanges more than by its HBM writes
             fl = sum(plane_flops(w, min(batch, w.n_views - b * batch)) for b in range(n_batches)) / n_batches
-            tflops = fl / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
-            kernels[dom]["algorithmic_flops_per_launch"] = fl
-            kernels[dom]["TFLOPs"] = tflops
-            roofline.update({"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK,
-                             "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK, 4),
-                             "algorithmic_flops_per_launch": fl,
-                             "hbm_achieved_GBps": round(achieved, 1),
-                             "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)})
+            tflops = fl / (kernels["planes"]["avg_ms"] * 1e-3) / 1e12
+            kernels["planes"]["algorithmic_flops_per_launch"] = fl
+            kernels["planes"]["TFLOPs"] = tflops
+            roofline["planes_fft"] = {"achieved": round(tflops, 2), "unit": "TFLOP/s", "peak": FP32_VECTOR_PEAK,
+                                      "frac": round(tflops / FP32_VECTOR_PEAK, 4),
+                                      "peak_without_packed_fp32": FP32_UNPACKED_PEAK,
+                                      "frac_without_packed_fp32": round(tflops / FP32_UNPACKED_PEAK, 4),
+                                      "flops_per_launch": fl}
         print(f"[bench] kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
     cpu = None
-    rel_l2 = None
+    rel_l2 = max_rel = None
     if not args.no_cpu and fourier:
         import oracle
         from threadpoolctl import threadpool_limits
@@ -289,6 +344,7 @@ def main():
                                              variant=args.variant)
             cpu_s = time.perf_counter() - t
         cpu = {"value": updates / cpu_s, "unit": "voxel*angle updates/s", "cores": 1, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"whole workload ({w.n_views} views, {w.n_vox}^3), {cpu_s:.1f} s "
                          "(numpy FP64 Fourier-space form, one thread)"}
         plan.fourier_reconstruct(d_img, vol, variant=args.variant, nsr=args.nsr, stream=stream)
@@ -298,7 +354,9 @@ def main():
         print(f"[bench] oracle {cpu_s:.1f}s; rel-L2 {rel_l2:.3g}", file=sys.stderr, flush=True)
     elif not args.no_cpu:
         import oracle
-        nv = min(args.cpu_views, w.n_views)
+        threads = host_threads(args.cpu_threads)
+        nv = args.cpu_views or max(min(threads, w.n_views), int(CPU_BUDGET_UPDATES // float(w.n_vox) ** 3))
+        nv = min(nv, w.n_views)
         views = np.arange(nv)
         geo = oracle.Geometry(w.n_vox, w.M, w.K if w.ewald else 1, w.voxel, w.wavelength, w.sigma, w.epsilon,
                               ewald=w.ewald, weight_mode=w.weight_mode, eps_sampling=w.eps_sampling,
@@ -306,28 +364,38 @@ def main():
         vox = None
         if args.cpu_voxels:
             vox = np.random.default_rng(7).integers(0, w.n_vox, size=(args.cpu_voxels, 3))
+        imgs64f = imgs.astype(np.float64)
         t = time.perf_counter()
-        ref = oracle.reconstruct_views(imgs.astype(np.float64), dirs, dist, geo, views=views, voxels=vox)
+        ref = oracle_threaded(imgs64f, dirs, dist, geo, views, threads, voxels=vox)
         cpu_s = time.perf_counter() - t
         nvox = w.n_vox ** 3 if vox is None else len(vox)
-        cpu = {"value": float(nvox) * nv / cpu_s, "unit": "voxel*angle updates/s", "cores": 1,
-               "kind": "oracle",
+        cpu = {"value": float(nvox) * nv / cpu_s, "unit": "voxel*angle updates/s", "cores": threads,
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": (f"{nv} of {w.n_views} views, " +
                           (f"full {w.n_vox}^3 volume" if vox is None else f"{nvox} seeded voxels") +
-                          f", {cpu_s:.1f} s (numpy FP64, single thread; includes the plan-stage weights)")}
-        # the same views through the HIP path (stage entry points), compared over all voxels
-        part = torch.zeros_like(vol)
-        st = torch.empty(plan.stack_shape(min(batch, nv)), dtype=torch.float32, device=dev)
-        for first in range(0, nv, batch):
-            nb = min(batch, nv - first)
-            plan.backpropagate(d_img[first:first + nb].contiguous(), first, nb, st, stream=stream)
-            plan.grid(st, first, nb, part, stream=stream)
-        torch.cuda.synchronize()
-        got = part.cpu().numpy().astype(np.float64)
+                          f", {cpu_s:.1f} s wall on {threads} threads (numpy FP64; views split over threads, "
+                          "partial sums added in order; includes the plan-stage weights)")}
+        if nv == w.n_views:
+            # the timed path's own output (the last timed step wrote vol)
+            plan.reconstruct(d_img, vol, stream=stream)
+            torch.cuda.synchronize()
+            got = vol.cpu().numpy().astype(np.float64)
+        else:
+            # the same views through the stage entry points, compared over all voxels
+            part = torch.zeros_like(vol)
+            st = torch.empty(plan.stack_shape(min(batch, nv)), dtype=plan.stack_dtype, device=dev)
+            for first in range(0, nv, batch):
+                nb = min(batch, nv - first)
+                plan.backpropagate(d_img[first:first + nb].contiguous(), first, nb, st, stream=stream)
+                plan.grid(st, first, nb, part, stream=stream)
+            torch.cuda.synchronize()
+            got = part.cpu().numpy().astype(np.float64)
         if vox is not None:
             got = got[vox[:, 0], vox[:, 1], vox[:, 2]]
         rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        print(f"[bench] oracle {cpu_s:.1f}s on {nv} views; rel-L2 {rel_l2:.3g}", file=sys.stderr, flush=True)
+        max_rel = float(np.abs(got - ref).max() / np.abs(ref).max())
+        print(f"[bench] oracle {cpu_s:.1f}s on {nv} views, {threads} threads; rel-L2 {rel_l2:.3g}, "
+              f"max {max_rel:.3g}", file=sys.stderr, flush=True)
 
     out = {
         "metric": "voxel*angle updates/s (DT backprop+gridding)",
@@ -352,6 +420,7 @@ def main():
                    **({"fourier_mode": args.fourier_mode, "operator_entries": plan.fourier_entries,
                        "variant": args.variant, "nsr": args.nsr} if fourier else {})},
         "rel_l2_vs_fp64": rel_l2,
+        "max_abs_err_rel_to_max_vs_fp64": max_rel,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

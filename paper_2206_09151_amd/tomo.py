@@ -148,10 +148,17 @@ def _stream_ptr(stream) -> int | None:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def _dptr(t) -> int:
-    import torch
+def _dptr(t, dtype=None, min_bytes: int = 0, name: str = "tensor") -> int:
+    """Device address of a contiguous device tensor, after checking its element type and
+    that it holds at least min_bytes: the kernels read and write exactly the sizes the
+    plan implies, so a short or mistyped buffer is refused here, before any launch."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
-        raise ValueError("expected a contiguous device tensor")
+        raise ValueError(f"{name}: expected a contiguous device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    have = t.numel() * t.element_size()
+    if have < min_bytes:
+        raise ValueError(f"{name}: holds {have} bytes, the call needs {min_bytes}")
     return t.data_ptr()
 
 
@@ -190,6 +197,15 @@ class Plan:
         if st != OK:
             raise TomoError(st, _LIB.tomo_last_error(self._h).decode())
 
+    def _images(self, t, nb: int) -> int:
+        return _dptr(t, torch.float32, 4 * nb * self.M * self.M, "images")
+
+    def _volume(self, t) -> int:
+        return _dptr(t, torch.float32, 4 * self.N ** 3, "volume")
+
+    def _planes(self, t, nb: int) -> int:
+        return _dptr(t, self.stack_dtype, int(_LIB.tomo_stack_bytes(self._h, nb)), "planes")
+
     @property
     def grid_rows(self) -> int:
         """Voxel rows per thread of the gridding kernel (autotuned with Params.tune)."""
@@ -214,38 +230,43 @@ class Plan:
 
     # ---------------------------------------------------------------- entry points
     def backpropagate(self, images, first: int, nb: int, planes, stream=None):
-        self._check(_LIB.tomo_backpropagate(self._h, _dptr(images), first, nb, _dptr(planes),
-                                            ctypes.c_void_p(_stream_ptr(stream))))
+        nb = int(nb)
+        self._check(_LIB.tomo_backpropagate(self._h, self._images(images, max(nb, 0)), first, nb,
+                                            self._planes(planes, max(nb, 0)), ctypes.c_void_p(_stream_ptr(stream))))
 
     def grid(self, planes, first: int, nb: int, volume, stream=None):
-        self._check(_LIB.tomo_grid(self._h, _dptr(planes), first, nb, _dptr(volume),
+        nb = int(nb)
+        self._check(_LIB.tomo_grid(self._h, self._planes(planes, max(nb, 0)), first, nb, self._volume(volume),
                                    ctypes.c_void_p(_stream_ptr(stream))))
 
     def reconstruct(self, images, volume, stream=None):
-        self._check(_LIB.tomo_reconstruct(self._h, _dptr(images), _dptr(volume),
+        self._check(_LIB.tomo_reconstruct(self._h, self._images(images, self.n), self._volume(volume),
                                           ctypes.c_void_p(_stream_ptr(stream))))
 
     def reconstruct_async(self, images, volume, stream=None):
         """Enqueue a whole reconstruction without waiting; domain errors surface at sync()."""
-        self._check(_LIB.tomo_reconstruct_async(self._h, _dptr(images), _dptr(volume),
+        self._check(_LIB.tomo_reconstruct_async(self._h, self._images(images, self.n), self._volume(volume),
                                                 ctypes.c_void_p(_stream_ptr(stream))))
 
     def sync(self, stream=None):
         self._check(_LIB.tomo_sync(self._h, ctypes.c_void_p(_stream_ptr(stream))))
 
     def filtered_spectra(self, images, first: int, nb: int, out, stream=None):
-        self._check(_LIB.tomo_filtered_spectra(self._h, _dptr(images), first, nb, _dptr(out),
+        nb = int(nb)
+        self._check(_LIB.tomo_filtered_spectra(self._h, self._images(images, max(nb, 0)), first, nb,
+                                               _dptr(out, torch.float32, 8 * max(nb, 0) * self.M * self.M, "out"),
                                                ctypes.c_void_p(_stream_ptr(stream))))
 
     def fourier_reconstruct(self, images, volume, variant: int = EQ11, nsr: float = 0.0, stream=None):
         """The Fourier-space form (eq. 11 or eq. 12 by 3D gridding, NSR filter)."""
-        self._check(_LIB.tomo_fourier_reconstruct(self._h, _dptr(images), int(variant), float(nsr), _dptr(volume),
-                                                  ctypes.c_void_p(_stream_ptr(stream))))
+        self._check(_LIB.tomo_fourier_reconstruct(self._h, self._images(images, self.n), int(variant), float(nsr),
+                                                  self._volume(volume), ctypes.c_void_p(_stream_ptr(stream))))
 
     def fourier_reconstruct_async(self, images, volume, variant: int = EQ11, nsr: float = 0.0, stream=None):
         """fourier_reconstruct enqueued without waiting; domain errors surface at sync()."""
-        self._check(_LIB.tomo_fourier_reconstruct_async(self._h, _dptr(images), int(variant), float(nsr),
-                                                        _dptr(volume), ctypes.c_void_p(_stream_ptr(stream))))
+        self._check(_LIB.tomo_fourier_reconstruct_async(self._h, self._images(images, self.n), int(variant),
+                                                        float(nsr), self._volume(volume),
+                                                        ctypes.c_void_p(_stream_ptr(stream))))
 
     def timing(self, enable: bool):
         self._check(_LIB.tomo_timing_enable(self._h, 1 if enable else 0))
@@ -278,8 +299,8 @@ class Batch:
         n = len(plans)
         self._keep = (list(plans), list(images), list(volumes))   # buffers bound into the graph
         hp = (ctypes.c_void_p * n)(*[p._h for p in plans])
-        hi = (ctypes.c_void_p * n)(*[_dptr(t) for t in images])
-        hv = (ctypes.c_void_p * n)(*[_dptr(t) for t in volumes])
+        hi = (ctypes.c_void_p * n)(*[p._images(t, p.n) for p, t in zip(plans, images)])
+        hv = (ctypes.c_void_p * n)(*[p._volume(t) for p, t in zip(plans, volumes)])
         out = ctypes.c_void_p()
         st = _LIB.tomo_batch_create(hp, hi, hv, n, int(lanes), ctypes.byref(out))
         if st != OK:

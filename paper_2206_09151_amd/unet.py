@@ -4,6 +4,8 @@ from __future__ import annotations
 
 import ctypes
 
+import torch
+
 from . import tomo
 
 _LIB = tomo.lib()
@@ -46,15 +48,26 @@ class Net:
     def _s(self, stream):
         return ctypes.c_void_p(tomo._stream_ptr(stream))
 
+    # every buffer is checked for its element type and size before the call: the kernels
+    # read and write exactly n^3 voxels and param_count() parameters
+    def _vol(self, t, name):
+        return tomo._dptr(t, torch.float32, 4 * self.n ** 3, name)
+
+    def _par(self, t, name):
+        return tomo._dptr(t, torch.float32, 4 * param_count(), name)
+
     def forward(self, params, x, y, stream=None):
-        self._check(_LIB.tomo_unet_forward(self._h, tomo._dptr(params), tomo._dptr(x), tomo._dptr(y), self._s(stream)))
+        self._check(_LIB.tomo_unet_forward(self._h, self._par(params, "params"), self._vol(x, "x"), self._vol(y, "y"),
+                                           self._s(stream)))
 
     def gradient(self, params, x, target, grad, loss, stream=None):
-        self._check(_LIB.tomo_unet_gradient(self._h, tomo._dptr(params), tomo._dptr(x), tomo._dptr(target),
-                                            tomo._dptr(grad), tomo._dptr(loss), self._s(stream)))
+        self._check(_LIB.tomo_unet_gradient(self._h, self._par(params, "params"), self._vol(x, "x"),
+                                            self._vol(target, "target"), self._par(grad, "grad"),
+                                            tomo._dptr(loss, torch.float64, 8, "loss"), self._s(stream)))
 
     def adam(self, params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-        self._check(_LIB.tomo_unet_adam(self._h, tomo._dptr(params), tomo._dptr(grad), tomo._dptr(m), tomo._dptr(v),
+        self._check(_LIB.tomo_unet_adam(self._h, self._par(params, "params"), self._par(grad, "grad"),
+                                        self._par(m, "m"), self._par(v, "v"),
                                         int(step), float(lr), float(beta1), float(beta2), float(eps),
                                         self._s(stream)))
 

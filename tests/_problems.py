@@ -28,6 +28,7 @@ class Problem:
     dist: np.ndarray
     images: np.ndarray            # float32 [n, M, M]
     vaxes: np.ndarray | None = None
+    i_in: float = 1.0             # flat-field intensity the images were made with
     extra: dict = field(default_factory=dict)
 
     @property
@@ -38,19 +39,29 @@ class Problem:
         import oracle
         return oracle.Geometry(self.n_vox, self.n_pix, self.n_planes if self.ewald else 1, self.voxel,
                                self.wavelength, self.sigma, self.epsilon, ewald=self.ewald,
-                               weight_mode=self.weight_mode)
+                               weight_mode=self.weight_mode, i_in=self.i_in)
 
     def params(self, **kw):
         from paper_2206_09151_amd import tomo
         return tomo.Params(n_vox=self.n_vox, n_angles=self.n, voxel_size=self.voxel,
                            wavelength=self.wavelength, sigma=self.sigma, epsilon=self.epsilon,
                            n_pix=self.n_pix, n_planes=self.n_planes if self.ewald else 0, ewald=self.ewald,
-                           weight_mode=self.weight_mode, **kw)
+                           weight_mode=self.weight_mode, i_in=self.i_in, **kw)
 
 
-def _born(seed, n_vox, n_pix, dx, lam, dirs, dist, sigma, width=1.2, count=20):
+def _born(seed, n_vox, n_pix, dx, lam, dirs, dist, sigma, width=1.2, count=20, i_in=1.0):
     ph = phantoms.draw_blobs(seed, n_vox, dx, 0.0, width * dx, 2e-5, sigma=sigma, count=count, support=0.4)
-    return forward.born_images(ph, dirs, n_pix, dx, lam, dist, sigma).astype(np.float32)
+    return forward.born_images(ph, dirs, n_pix, dx, lam, dist, sigma, i_in).astype(np.float32)
+
+
+def pole_directions(seed: int, n: int) -> np.ndarray:
+    """Directions with the detector-frame rule's special cases: exactly +y and -y, one
+    within 1e-7 of +y (still taken as a pole), one 2e-6 away (not a pole), then
+    directions uniform on the sphere."""
+    e = 1e-7
+    near = np.array([[e, np.sqrt(1 - e * e), 0.0], [0.0, np.sqrt(1 - 4e-12), -2e-6]])
+    fixed = np.vstack([[0.0, 1.0, 0.0], [0.0, -1.0, 0.0], near])
+    return np.vstack([fixed, scan.uniform_sphere(seed, n - len(fixed))])
 
 
 def make(name: str) -> Problem:
@@ -169,8 +180,41 @@ def make(name: str) -> Problem:
         lam, sig = 0.05e-10, -0.1
         imgs = _born(22, N, M, dx, lam, dirs, dist, sig, count=30)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+    if name == "iin32":
+        # flat field I_in = 0.7; sampling-matrix weights and curvature keep the q = 0 term,
+        # so a dropped or inverted I_in changes the result
+        n, N, M, K = 12, 32, 32, 32
+        dirs = scan.single_axis_jitter(26, n, 180.0, 5.0)
+        dist = np.full(n, 50e-10)
+        lam, sig = 0.1e-10, 0.0
+        imgs = _born(26, N, M, dx, lam, dirs, dist, sig, i_in=0.7)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "sampling", dirs, dist, imgs, i_in=0.7)
+    if name == "m256iin":
+        # I_in = 0.7 on the 256-pixel detector path
+        n, N, M, K = 4, 40, 256, 40
+        dirs = scan.single_axis_jitter(27, n, 180.0, 5.0)
+        dist = np.full(n, 80e-10)
+        lam, sig = 0.05e-10, 0.0
+        imgs = _born(27, N, M, dx, lam, dirs, dist, sig, count=24, i_in=0.7)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "sampling", dirs, dist, imgs, i_in=0.7)
+    if name == "pole24":
+        # illumination along +-y and within 1e-6 of it: the frame takes lab x as reference
+        n, N, M, K = 8, 24, 32, 24
+        dirs = pole_directions(28, n)
+        dist = np.full(n, 40e-10)
+        lam, sig = 0.1e-10, 0.1
+        imgs = _born(28, N, M, dx, lam, dirs, dist, sig, count=12)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+    if name == "m128":
+        # the headline detector size (radix 16 x 8 FFT) at the full volume, few views
+        n, N, M, K = 4, 128, 128, 128
+        dirs = scan.single_axis(n, 180.0, offset_deg=9.0)
+        dist = np.full(n, 60e-10)
+        lam, sig = 0.0197e-10, 0.0
+        imgs = _born(29, N, M, dx, lam, dirs, dist, sig, count=60)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
     raise KeyError(name)
 
 
 SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32",
-         "m256", "m256sph", "m160", "m192", "narrow48"]
+         "m256", "m256sph", "m160", "m192", "narrow48", "iin32", "m256iin", "pole24", "m128"]

@@ -1,12 +1,15 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Tolerance: relative L2 <= 1e-5 for FP32 results against FP64 (the stated bar
-for FP32); per-stage checks are tighter where the arithmetic allows.
+for FP32), and beside it an element-wise bound max|got - ref| <= 1e-5 max|ref|, so
+that a few wrong voxels (a mis-mapped tile, a ragged edge) cannot hide under the
+volume norm; per-stage checks are tighter where the arithmetic allows.
 """
 import numpy as np
 import pytest
 
 import oracle
+import _oracle_par
 import _problems
 
 torch = pytest.importorskip("torch")
@@ -26,6 +29,15 @@ def _rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def assert_close(got, ref, tol, what=""):
+    """rel-L2 <= tol and max|got - ref| <= tol * max|ref|."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    rel = _rel(got, ref)
+    worst = float(np.abs(got - ref).max() / np.abs(ref).max())
+    assert rel < tol and worst < tol, (what, rel, worst)
+
+
 def _oracle_inputs(pb):
     return pb.images.astype(np.float64)
 
@@ -40,7 +52,8 @@ def _plan(pb, **kw):
     return tomo.Plan(pb.params(**kw), pb.dirs, pb.dist, vaxes=pb.vaxes)
 
 
-@pytest.mark.parametrize("name", ["axis32", "sphere45", "sampling32", "m96", "m256", "m160", "m192"])
+@pytest.mark.parametrize("name", ["axis32", "sphere45", "sampling32", "m96", "m256", "m160", "m192", "iin32",
+                                  "m256iin", "pole24", "m128"])
 def test_filtered_spectra_match_oracle(dev, name):
     pb = _problems.make(name)
     plan = _plan(pb, angle_batch=pb.n)
@@ -53,11 +66,12 @@ def test_filtered_spectra_match_oracle(dev, name):
     geo = pb.oracle_geometry()
     u, v, d = oracle.frames(pb.dirs, pb.vaxes)
     W = oracle.density_weights(u, v, d, geo)
-    P = oracle.filtered_spectra(oracle.spectrum(oracle.contrast(_oracle_inputs(pb))), pb.dist, W, geo)
-    assert _rel(got, P) < 2e-6, _rel(got, P)
+    P = oracle.filtered_spectra(oracle.spectrum(oracle.contrast(_oracle_inputs(pb), pb.i_in)), pb.dist, W, geo)
+    assert_close(got, P, 2e-6, name)
 
 
-@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "oddk16", "m80", "m256", "m256sph", "m160", "m192"])
+@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "oddk16", "m80", "m256", "m256sph", "m160",
+                                  "m192", "m128", "iin32", "m256iin"])
 def test_plane_stacks_match_oracle(dev, name):
     pb = _problems.make(name)
     plan = _plan(pb, angle_batch=pb.n)
@@ -69,13 +83,14 @@ def test_plane_stacks_match_oracle(dev, name):
     geo = pb.oracle_geometry()
     u, v, d = oracle.frames(pb.dirs, pb.vaxes)
     W = oracle.density_weights(u, v, d, geo)
-    P = oracle.filtered_spectra(oracle.spectrum(oracle.contrast(_oracle_inputs(pb))), pb.dist, W, geo)
+    P = oracle.filtered_spectra(oracle.spectrum(oracle.contrast(_oracle_inputs(pb), pb.i_in)), pb.dist, W, geo)
     for i in range(pb.n):
         ref = np.transpose(oracle.depth_planes(P[i], geo), (1, 0, 2))  # -> [row][plane][col]
-        assert _rel(got[i], ref) < TOL, (i, _rel(got[i], ref))
+        assert_close(got[i], ref, TOL, (name, i))
 
 
-@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "narrow48"])
+@pytest.mark.parametrize("name", ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "narrow48",
+                                  "pole24"])
 def test_grid_of_oracle_planes_matches_oracle_gather(dev, name):
     """Gridding alone: the oracle's FP64 planes, rounded to FP32, gridded by both sides."""
     pb = _problems.make(name)
@@ -83,7 +98,7 @@ def test_grid_of_oracle_planes_matches_oracle_gather(dev, name):
     geo = pb.oracle_geometry()
     u, v, d = oracle.frames(pb.dirs, pb.vaxes)
     W = oracle.density_weights(u, v, d, geo)
-    P = oracle.filtered_spectra(oracle.spectrum(oracle.contrast(_oracle_inputs(pb))), pb.dist, W, geo)
+    P = oracle.filtered_spectra(oracle.spectrum(oracle.contrast(_oracle_inputs(pb), pb.i_in)), pb.dist, W, geo)
     stacks = np.stack([oracle.depth_planes(P[i], geo) for i in range(pb.n)]).astype(np.float32)
     ref = np.zeros((pb.n_vox,) * 3)
     for i in range(pb.n):
@@ -92,7 +107,7 @@ def test_grid_of_oracle_planes_matches_oracle_gather(dev, name):
     vol = torch.zeros((pb.n_vox,) * 3, dtype=torch.float32, device=dev)
     plan.grid(dev_st, 0, pb.n, vol)
     torch.cuda.synchronize()
-    assert _rel(vol.cpu().numpy(), ref) < 2e-6, _rel(vol.cpu().numpy(), ref)
+    assert_close(vol.cpu().numpy(), ref, 2e-6, name)
 
 
 @pytest.mark.parametrize("name", _problems.SMALL)
@@ -103,9 +118,9 @@ def test_reconstruct_matches_oracle(dev, name):
     vol = torch.full((pb.n_vox,) * 3, float("nan"), dtype=torch.float32, device=dev)
     plan.reconstruct(img, vol)
     got = vol.cpu().numpy()
-    ref = oracle.reconstruct(_oracle_inputs(pb), pb.dirs, pb.dist, pb.oracle_geometry(), vaxes=pb.vaxes)
+    ref = _oracle_par.reconstruct_views(_oracle_inputs(pb), pb.dirs, pb.dist, pb.oracle_geometry(), vaxes=pb.vaxes)
     assert np.isfinite(got).all()
-    assert _rel(got, ref) < TOL, _rel(got, ref)
+    assert_close(got, ref, TOL, name)
 
 
 def test_reconstruct_is_bitwise_deterministic(dev):
@@ -231,7 +246,7 @@ def test_autotuned_gridding_gives_identical_volumes(name):
         assert np.linalg.norm(out[0] - out[1]) <= 1e-6 * np.linalg.norm(out[0])
 
 
-@pytest.mark.parametrize("name", ["sphere45", "vaxes32", "m256sph", "m192", "sampling32"])
+@pytest.mark.parametrize("name", ["sphere45", "vaxes32", "m256sph", "m192", "sampling32", "pole24"])
 def test_cubic_tile_gridding_matches_oracle(name):
     """The cubic-tile gridding kernel (tune = 2) over general frames, whole volume."""
     tomo = _tomo()
@@ -245,4 +260,29 @@ def test_cubic_tile_gridding_matches_oracle(name):
                               vaxes=prob.vaxes)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
     print(f"cubic tiles {name}: rel-L2 {err:.3g}", flush=True)
-    assert err <= 1e-5
+    assert_close(got, want, 1e-5, name)
+
+
+def test_binding_refuses_short_or_mistyped_buffers(dev):
+    """The binding checks element type and size against the plan before the call, so a
+    buffer the kernels would overrun never reaches a launch."""
+    tomo = _tomo()
+    pb = _problems.make("axis32")
+    plan = _plan(pb, angle_batch=4)
+    img = torch.from_numpy(pb.images).to(dev)
+    vol = torch.zeros((pb.n_vox,) * 3, dtype=torch.float32, device=dev)
+    st = torch.empty(plan.stack_shape(4), dtype=torch.float32, device=dev)
+    cases = [
+        lambda: plan.backpropagate(img, 0, 4, st.to(torch.bfloat16)),                  # planes of another type
+        lambda: plan.backpropagate(img, 0, 4, st[:3]),                                 # 3 stacks for 4 views
+        lambda: plan.backpropagate(img[:2].contiguous(), 0, 4, st),                    # 2 images for 4 views
+        lambda: plan.grid(st, 0, 4, vol[:-1]),                                         # volume one slab short
+        lambda: plan.grid(st, 0, 4, vol.double()),                                     # volume of doubles
+        lambda: plan.reconstruct(img[:-1].contiguous(), vol),                          # one image short
+        lambda: plan.reconstruct(img.half(), vol),                                     # images of halves
+        lambda: plan.filtered_spectra(img, 0, 4, torch.empty((4, 32, 32), device=dev)),  # no imaginary parts
+    ]
+    for bad in cases:
+        with pytest.raises(ValueError):
+            bad()
+    assert torch.count_nonzero(vol) == 0                                              # nothing ran

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import oracle.utr as utr
+import test_oracle_limits as limits
 import test_oracle_pins as pins
 
 
@@ -60,7 +61,39 @@ def _ramp_wrong_axis(u, v, d, geo):
     return utr.axis_angle_weights(d)[:, None, None] * np.abs(qy)[None]
 
 
+def _contrast_inverted(images, i_in=1.0):
+    return np.log(i_in / np.asarray(images, dtype=np.float64))
+
+
+def _contrast_without_flat_field(images, i_in=1.0):
+    return np.log(np.asarray(images, dtype=np.float64))
+
+
+def _lin_taps_swapped(f, size):
+    i0 = np.floor(f).astype(np.int64)
+    t = f - i0
+    out = []
+    for c in (0, 1):
+        i = i0 + c
+        w = (1.0 - t) if c else t                     # weights on the wrong neighbours
+        ok = (i >= 0) & (i < size)
+        out.append((np.clip(i, 0, size - 1), np.where(ok, w, 0.0)))
+    return out
+
+
+def _bracket_cos_for_sin(chi, eps, ewald):
+    c = np.cos(chi)
+    re = c / (c * c + eps)                            # the wrong CTF branch in the real part
+    return re.astype(complex) if not ewald else re - 1j * c / (c * c + eps)
+
+
 MUTATIONS = [
+    ("contrast", _contrast_inverted, limits.test_contrast_is_log_of_intensity_over_flat_field),
+    ("contrast", _contrast_without_flat_field, limits.test_flat_field_intensity_enters_as_a_divisor),
+    ("_lin_taps", _lin_taps_swapped, lambda: limits.test_pct_limit_equals_textbook_filtered_backprojection(15, 16)),
+    ("ctf_bracket", _bracket_cos_for_sin, lambda: limits.test_pct_limit_equals_textbook_filtered_backprojection(16, 16)),
+    ("frames", _frames_left_handed, limits.test_central_sections_of_the_reconstruction_match_projected_delta),
+    ("plane_depths", _depths_off_by_one, limits.test_curvature_terms_cancel_between_opposite_views),
     ("depth_planes", _flip_propagator, pins.test_ewald_curvature_matters_when_dof_is_small),
     ("spectrum", _transposed_spectrum, pins.test_ct_limit_recovers_phantom_from_fresnel_images),
     ("ctf_bracket", _bracket_wrong_imag_sign, pins.test_bracket_solves_opposite_pair_eq10),
@@ -72,7 +105,7 @@ MUTATIONS = [
 ]
 
 
-@pytest.mark.parametrize("name,bad,pin", MUTATIONS, ids=[f"{m[0]}-{m[1].__name__}" for m in MUTATIONS])
+@pytest.mark.parametrize("name,bad,pin", MUTATIONS, ids=[f"{m[0]}-{getattr(m[1], '__name__', '')}-{i}" for i, m in enumerate(MUTATIONS)])
 def test_planted_mistake_is_caught(monkeypatch, name, bad, pin):
     monkeypatch.setattr(utr, name, bad)
     if hasattr(oracle, name):
