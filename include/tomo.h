@@ -31,7 +31,8 @@
  *     caller; they are never freed or retained by the library.
  *   - Streams are hipStream_t passed as void*; NULL means the null stream.
  *     Every call enqueues asynchronously on its stream except where stated.
- *     A plan is used by one stream at a time; there is no global state.
+ *     A plan is used by one stream at a time; apart from the per-GPU workspace of
+ *     tomo_backpropagate_noalloc there is no global state.
  *
  * Errors: every call returns tomo_status and never aborts or throws.
  *   TOMO_EINVAL       bad argument (null pointer, non-unit direction, bad range)
@@ -133,6 +134,27 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
  * Uses the plan's spectrum slots of those views (calls on one plan are serial). */
 tomo_status tomo_backpropagate(tomo_plan_t plan, const float* d_images, int32_t first, int32_t nb,
                                void* d_planes, void* stream);
+
+/* tomo_backpropagate for callers that cannot allocate device memory (work recorded under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and the same output, bit for bit, but the filtered spectra of the nb views
+ * (16 M^2 bytes per view) live in a static device workspace of
+ * TOMO_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on (from the
+ * first plan made there until the process ends) instead of the plan's workspace.  The call
+ * allocates no device or host memory on success: no hipMalloc, hipFree or allocating
+ * library routine (plan timing is not recorded for it).  Arguments and layouts as
+ * tomo_backpropagate; the plan (made beforehand) still provides its tables and the FP16
+ * per-view scales.
+ *   TOMO_EINVAL  bad range or pointer, or nb * 16 M^2 > TOMO_NOALLOC_SCRATCH_BYTES (the
+ *                message says so; split the views over several calls)
+ *   TOMO_EDEVICE the workspace's device address could not be obtained or a launch failed
+ * Every call on one GPU uses that GPU's single workspace: calls that overlap in time on one
+ * GPU (on different streams, or from different plans or threads) race and must be
+ * serialised by the caller.  A call leaves the spectra of its views in the workspace; each
+ * call overwrites what it reads, so nothing needs clearing between calls. */
+#define TOMO_NOALLOC_SCRATCH_BYTES (32u << 20)
+tomo_status tomo_backpropagate_noalloc(tomo_plan_t plan, const float* d_images, int32_t first, int32_t nb,
+                                       void* d_planes, void* stream);
 
 /* Grid plane stacks of views [first, first+nb) into the volume: for every voxel
  * the trilinear value of each view's stack at the voxel's view-frame position

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -49,7 +50,9 @@ struct tomo_plan_s {
   size_t op_entries = 0;
   bool same_R = true;
   double R0 = 0.0;
-  std::string err;
+  void* scratch = nullptr;              // this device's copy of the allocation-free workspace
+  std::string err;                      // capacity reserved at plan time (error paths of the
+                                        // allocation-free call assign within it)
   // tracing: events around launches while timing is on
   struct Rec {
     int kind;
@@ -62,9 +65,19 @@ struct tomo_plan_s {
   long long launches[TOMO_TIMING_KINDS] = {};
 };
 
+static __device__ __align__(256) unsigned char scratch[TOMO_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_plan_error;
+
+// Workspace of tomo_backpropagate_noalloc: the filtered spectra of the views of one call.
+// A file-scope device array (one copy per GPU, kept until the process ends); host code
+// reaches it only through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(TOMO_NOALLOC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
@@ -200,6 +213,23 @@ void axis_weights(const double* dirs, int n, std::vector<ViewGeom>& g) {
     const double prv = (k > 0) ? phi[order[k - 1]] : phi[order[n - 1]] - kPi;
     g[order[k]].a = 0.5 * (nxt - prv);
   }
+}
+
+// Device address of the current device's copy of `scratch`, looked up once per device.
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 template <class T>
@@ -575,6 +605,13 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
   }
+  // address of this device's allocation-free workspace (looked up again by that call if
+  // this fails); the error string gets room for that call's messages
+  if (scratch_address(&pl->scratch) != hipSuccess) {
+    pl->scratch = nullptr;
+    (void)hipGetLastError();
+  }
+  pl->err.reserve(256);
   *out = pl;
   return TOMO_OK;
 }
@@ -622,6 +659,50 @@ tomo_status tomo_backpropagate(tomo_plan_t pl, const float* d_images, int32_t fi
                                d_planes, pl->K, pl->npairs, nb, pl->d_scale + first, s, pl->d_tw2_inv);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "planes kernel");
+  return TOMO_OK;
+}
+
+// Message into the plan's reserved error string without growing it.
+static tomo_status fail_fixed(tomo_plan_t pl, tomo_status st, const char* a, const char* b = nullptr) {
+  pl->err.clear();
+  const size_t cap = pl->err.capacity();
+  for (const char* part : {a, b}) {
+    if (!part) continue;
+    const size_t room = cap > pl->err.size() ? cap - pl->err.size() : 0;
+    pl->err.append(part, std::min(room, std::strlen(part)));
+  }
+  return st;
+}
+
+tomo_status tomo_backpropagate_noalloc(tomo_plan_t pl, const float* d_images, int32_t first, int32_t nb,
+                                       void* d_planes, void* stream) {
+  if (!pl) return TOMO_EINVAL;
+  pl->err.clear();
+  if (nb == 0) return TOMO_OK;
+  if (!d_images || !d_planes) return fail_fixed(pl, TOMO_EINVAL, "null device pointer");
+  if (first < 0 || nb < 0 || first > pl->n || nb > pl->n - first)
+    return fail_fixed(pl, TOMO_EINVAL, "view range [first, first+nb) outside [0, n_angles)");
+  if (size_t(nb) * pl->M * pl->M * sizeof(float4) > kScratchBytes)
+    return fail_fixed(pl, TOMO_EINVAL,
+                      "nb views need more than TOMO_NOALLOC_SCRATCH_BYTES (16 M^2 bytes per view); pass fewer views");
+  if (!pl->scratch) {
+    const hipError_t e = scratch_address(&pl->scratch);
+    if (e != hipSuccess) {
+      pl->scratch = nullptr;
+      return fail_fixed(pl, TOMO_EDEVICE, "workspace address: ", hipGetErrorString(e));
+    }
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t mm = size_t(pl->M) * pl->M;
+  float4* q = static_cast<float4*>(pl->scratch);
+  float* scale = pl->p.plane_dtype == TOMO_F16 ? pl->d_scale + first : nullptr;
+  hipError_t e = tomo::launch_spectra(pl->M, d_images, pl->d_filt + size_t(first) * mm, pl->d_tw_fwd, q,
+                                      pl->d_status, 1.0 / pl->p.i_in, scale, nb, s, pl->d_tw2_fwd,
+                                      pl->d_l1part + size_t(4) * first);
+  if (e != hipSuccess) return fail_fixed(pl, TOMO_EDEVICE, "spectra kernel: ", hipGetErrorString(e));
+  e = tomo::launch_planes(pl->M, pl->p.plane_dtype, q, pl->d_prop, pl->d_tw_inv, d_planes, pl->K, pl->npairs, nb,
+                          pl->d_scale + first, s, pl->d_tw2_inv);
+  if (e != hipSuccess) return fail_fixed(pl, TOMO_EDEVICE, "planes kernel: ", hipGetErrorString(e));
   return TOMO_OK;
 }
 

@@ -31,9 +31,10 @@ EXPORTED = [
     "tomo_timing_enable", "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_reconstruct_async",
     "tomo_fourier_entries",
     "tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_error", "tomo_batch_destroy",
-    "tomo_grid_rows",
+    "tomo_grid_rows", "tomo_backpropagate_noalloc",
 ]
 KERNEL_KINDS = ("spectra", "planes", "grid", "fgrid", "finverse")
+NOALLOC_SCRATCH_BYTES = 32 << 20    # TOMO_NOALLOC_SCRATCH_BYTES
 FOURIER_OPERATOR, FOURIER_SPLAT = 1, 2
 EQ11, EQ12 = 11, 12
 
@@ -64,6 +65,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     dptr = ctypes.POINTER(ctypes.c_double)
     lib.tomo_plan.argtypes = [ctypes.POINTER(TomoParams), dptr, dptr, dptr, vp, ctypes.POINTER(vp)]
     lib.tomo_backpropagate.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.tomo_backpropagate_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.tomo_grid.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.tomo_reconstruct.argtypes = [vp, vp, vp, vp]
     lib.tomo_reconstruct_async.argtypes = [vp, vp, vp, vp]
@@ -98,7 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tomo_batch_destroy.argtypes = [vp]
     for name in ("tomo_batch_create", "tomo_batch_launch", "tomo_batch_sync", "tomo_batch_destroy"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("tomo_plan", "tomo_backpropagate", "tomo_grid", "tomo_reconstruct", "tomo_reconstruct_async", "tomo_sync",
+    for name in ("tomo_plan", "tomo_backpropagate", "tomo_backpropagate_noalloc", "tomo_grid", "tomo_reconstruct", "tomo_reconstruct_async", "tomo_sync",
                  "tomo_filtered_spectra", "tomo_destroy", "tomo_batch_capacity", "tomo_timing_enable",
                  "tomo_timing_read", "tomo_fourier_reconstruct", "tomo_fourier_reconstruct_async"):
         getattr(lib, name).restype = ctypes.c_int
@@ -233,6 +235,14 @@ class Plan:
         nb = int(nb)
         self._check(_LIB.tomo_backpropagate(self._h, self._images(images, max(nb, 0)), first, nb,
                                             self._planes(planes, max(nb, 0)), ctypes.c_void_p(_stream_ptr(stream))))
+
+    def backpropagate_noalloc(self, images, first: int, nb: int, planes, stream=None):
+        """backpropagate without any allocation: the spectra live in the library's static
+        per-GPU workspace (at most NOALLOC_SCRATCH_BYTES / (16 M^2) views per call)."""
+        nb = int(nb)
+        self._check(_LIB.tomo_backpropagate_noalloc(self._h, self._images(images, max(nb, 0)), first, nb,
+                                                    self._planes(planes, max(nb, 0)),
+                                                    ctypes.c_void_p(_stream_ptr(stream))))
 
     def grid(self, planes, first: int, nb: int, volume, stream=None):
         nb = int(nb)
