@@ -92,7 +92,9 @@ def kernel_source_hash() -> str:
     """Hash of the kernel sources' code: // comments, trailing blanks and empty lines are
     left out, so that editing a comment does not orphan the stored counter summaries."""
     h = hashlib.sha256()
-    for f in ("fft.hpp", "geom.hpp", "tomo_kernels.hip", "fourier_kernels.hip"):
+    csrc = os.path.join(ROOT, "paper_2206_09151_amd", "csrc")
+    sizes = sorted(f for f in os.listdir(csrc) if f.startswith("fft_sizes"))
+    for f in ["fft.hpp", "fft_kernels.hpp", "geom.hpp", "tomo_kernels.hip", "fourier_kernels.hip"] + sizes:
         with open(os.path.join(ROOT, "paper_2206_09151_amd", "csrc", f), encoding="utf-8") as fh:
             for line in fh:
                 code = line.split("//", 1)[0].rstrip()

@@ -121,8 +121,11 @@ typedef struct {
  *   dist   host double [n], R_n (finite)
  *   stream hipStream_t the plan's set-up work runs on (synchronised before return)
  *   out    receives the plan; untouched on error.
- * Supported: M in {16, 32, 48, 64, 80, 96, 128, 160, 192, 256}; N in [2, 1024]; K in [1, 2N];
- * with fourier = 1 or 2 also N in {16, 32, 48, 64, 80, 96, 128, 256}. */
+ * Supported: M every 2^a 3^b 5^c in [16, 256] (others: TOMO_EUNSUPPORTED); N in [2, 1024];
+ * K in [1, 2N]; with fourier = 1 or 2 also N in {16, 32, 48, 64, 80, 96, 128, 256}.  Single-axis
+ * plans whose stack rows are whole 16-byte chunks (M a multiple of 4, or of 8 for 16-bit
+ * planes, and M - N even) use the single-axis gridding kernel; the others use the
+ * general-frame kernels (the cubic-tile kernel when M is not such a multiple). */
 tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* vaxes,
                       const double* dist, void* stream, tomo_plan_t* out);
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libtomo.so")
-SOURCES = ["tomo_kernels.hip", "fourier_kernels.hip", "tomo_host.hip", "unet_kernels.hip", "unet_host.hip"]
+SOURCES = ["tomo_kernels.hip", "fourier_kernels.hip", "tomo_host.hip", "unet_kernels.hip", "unet_host.hip"] + [
+    f"fft_sizes_{g}.hip" for g in "abcdefghij"]
 ARCH = "gfx950"
 
 

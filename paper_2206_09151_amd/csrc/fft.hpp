@@ -1,7 +1,7 @@
 // Register DFT codelets and an LDS-staged 2D FFT for one workgroup on gfx950.
 //
-// The 2D transform of an M x M complex block (M = R1 * R2, R2 | R1) runs with
-// M * R2 threads.  Each 1D pass is a two-stage Cooley-Tukey split of the index
+// The 2D transform of an M x M complex block (M = R1 * R2) runs with M * R2 threads.
+// Each 1D pass is a two-stage Cooley-Tukey split of the index
 //   k = r + R2*m  ->  X[s + R1*k2] = sum_r W_R2^(r k2) W_M^(r s) sum_m W_R1^(m s) x[r + R2 m]
 // stage 1: a radix-R1 DFT in registers per (line, r), then the twiddle W_M^(r s);
 // stage 2: radix-R2 DFTs over r, after one exchange through LDS.  Between the
@@ -177,15 +177,20 @@ struct Dft {
 };
 
 // ---------------------------------------------------------------- 2D FFT in LDS
-// Thread mapping (t = threadIdx.x, T = M*R2 threads):
+// Thread mapping (t = threadIdx.x, T = M*R2 threads, E = ceil(R1/R2)):
 //   column stage 1: line = t % M (column kx), r = t / M; holds x[m] = Z[r + R2 m][line]
 //   row stage 2 output: sg = t % R2, y = t / R2; holds out[e*R2 + k2] =
-//       b[y][sg*(R1/R2) + e + R1*k2]     (e < R1/R2, k2 < R2)
+//       b[y][sg*E + e + R1*k2]     (e < E, k2 < R2), valid where s = sg*E + e < R1
+// When R2 does not divide R1 the last stage-2 slots of some threads are idle (has_s).
 template <int M_, int R1_, int R2_>
 struct Fft2Shape {
   static constexpr int M = M_, R1 = R1_, R2 = R2_;
   static constexpr int T = M * R2;
-  static constexpr int E = R1 / R2;           // stage-2 DFTs per thread
+  static constexpr int E = (R1 + R2 - 1) / R2;  // stage-2 DFTs per thread
+  static constexpr bool EXACT = (E * R2 == R1);
+  static constexpr int XN = E * R2 > R1 ? E * R2 : R1;   // registers per thread (complex)
+  // stage-1 output index s = sg*E + e exists
+  __device__ __forceinline__ static bool has_s(int s) { return EXACT || s < R1; }
   static constexpr int TP = M + 1;            // transpose pitch (float2)
   static constexpr int SP = R2 * M + 2;       // exchange pitch per stage-1 output index s
   static constexpr int LDS_ELEMS = (M * TP > R1 * SP) ? M * TP : R1 * SP;
@@ -194,14 +199,14 @@ struct Fft2Shape {
   // parts, through a float buffer of half the bytes
   static constexpr int SPF = R2 * M + 4;      // float exchange pitch per s
   static constexpr int LDS_SPLIT_FLOATS = (M * TP > R1 * SPF) ? M * TP : R1 * SPF;
-  static_assert(R1 * R2 == M && R1 % R2 == 0, "M = R1*R2 with R2 | R1");
+  static_assert(R1 * R2 == M && R1 >= R2, "M = R1*R2 with R1 >= R2");
   static_assert(T <= 1024, "at most 1024 threads");
-  static_assert(R1 * (R2 * M + 4) <= LDS_SPLIT_FLOATS, "paired exchange fits the split buffer");
+  static_assert(!EXACT || R1 * (R2 * M + 4) <= LDS_SPLIT_FLOATS, "paired exchange fits the split buffer");
 };
 
 // Twiddle table tw[k] = exp(sgn i 2 pi k / M), FP64-rounded; index (r*s) mod M.
 template <class S, bool INV>
-__device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restrict__ lds,
+__device__ __forceinline__ void fft2_block(float2 (&x)[S::XN], float2* __restrict__ lds,
                                            const float2* __restrict__ tw) {
   constexpr int M = S::M, R1 = S::R1, R2 = S::R2, E = S::E, TP = S::TP, SP = S::SP;
   const int t = threadIdx.x;
@@ -226,6 +231,7 @@ __device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restric
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = sg * E + e;
+      if (!S::has_s(s)) continue;
       float2 y[R2];
 #pragma unroll
       for (int rr = 0; rr < R2; ++rr) y[rr] = lds[s * SP + rr * M + line];
@@ -238,6 +244,7 @@ __device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restric
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = sg * E + e;
+      if (!S::has_s(s)) continue;
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) lds[(s + R1 * k2) * TP + line] = x[e * R2 + k2];
     }
@@ -260,6 +267,7 @@ __device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restric
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = sg * E + e;
+      if (!S::has_s(s)) continue;
       float2 v[R2];
 #pragma unroll
       for (int rr = 0; rr < R2; ++rr) v[rr] = lds[s * SP + rr * M + y];
@@ -277,7 +285,7 @@ __device__ __forceinline__ void fft2_block(float2 (&x)[S::R1], float2* __restric
 // LDS and overlap each other's barriers.  No extra registers: a component is read
 // back into the slots its own values were written from.
 template <class S, bool INV>
-__device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __restrict__ lds,
+__device__ __forceinline__ void fft2_block_split(float2 (&x)[S::XN], float* __restrict__ lds,
                                                  const float2* __restrict__ tw) {
   constexpr int M = S::M, R1 = S::R1, R2 = S::R2, E = S::E, TP = S::TP, SPF = S::SPF;
   const int t = threadIdx.x;
@@ -293,7 +301,7 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
 #pragma unroll
   for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
   // ---- exchange 1: x[s] of (line, r) -> thread (line, sgc) gets x[e*R2 + rr] = X1[s = sgc*E + e][rr]
-  if constexpr (E % 2 == 0) {
+  if constexpr (E % 2 == 0 && S::EXACT) {
     // the values of stage-1 outputs s and s+1 side by side (s even): each thread writes and
     // reads 8 bytes at a time, half the LDS instructions for the same bytes
     float2* lds2 = reinterpret_cast<float2*>(lds);
@@ -325,6 +333,7 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int s = sgc * E + e;
+        if (!S::has_s(s)) continue;
 #pragma unroll
         for (int rr = 0; rr < R2; ++rr) {
           const float v = lds[s * SPF + rr * M + line];
@@ -337,13 +346,15 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
   }
   // ---- column pass, stage 2 (radix R2 over rr), in place per e
 #pragma unroll
-  for (int e = 0; e < E; ++e) Dft<R2, INV>::run(&x[e * R2]);
+  for (int e = 0; e < E; ++e)
+    if (S::has_s(sgc * E + e)) Dft<R2, INV>::run(&x[e * R2]);
   // ---- transpose: (row Y = s + R1*k2, column line) -> thread (row line, r) gets columns r + R2*m
 #pragma unroll
   for (int comp = 0; comp < 2; ++comp) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int s = sgc * E + e;
+      if (!S::has_s(s)) continue;
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) lds[(s + R1 * k2) * TP + line] = comp ? x[e * R2 + k2].y : x[e * R2 + k2].x;
     }
@@ -362,7 +373,7 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
   for (int s = 1; s < R1; ++s) x[s] = cmul(x[s], tw[(r * s) % M]);
   // ---- exchange 3: thread (sg = t % R2, y = t / R2) gets X1[s = sg*E + e][rr] of row y
   const int sg = t % R2, yy = t / R2;
-  if constexpr (E % 2 == 0) {
+  if constexpr (E % 2 == 0 && S::EXACT) {
     float2* lds2 = reinterpret_cast<float2*>(lds);
     constexpr int SP2 = R2 * M + 4;
 #pragma unroll
@@ -392,6 +403,7 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int s = sg * E + e;
+        if (!S::has_s(s)) continue;
 #pragma unroll
         for (int rr = 0; rr < R2; ++rr) {
           const float v = lds[s * SPF + rr * M + yy];
@@ -403,7 +415,8 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::R1], float* __re
     }
   }
 #pragma unroll
-  for (int e = 0; e < E; ++e) Dft<R2, INV>::run(&x[e * R2]);
+  for (int e = 0; e < E; ++e)
+    if (S::has_s(sg * E + e)) Dft<R2, INV>::run(&x[e * R2]);
 }
 
 }  // namespace tomo

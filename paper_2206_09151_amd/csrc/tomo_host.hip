@@ -21,6 +21,7 @@ using tomo::ViewGeom;
 struct tomo_plan_s {
   tomo_params p{};
   int N = 0, M = 0, K = 0, n = 0, npairs = 0, batch = 0;
+  int split = 1;                // block split of the detector-size FFT (M = P H for M > 200)
   bool axis_fast = false;
   int grid_rows = 8;            // gridding variant: 8 or 4 voxel rows per thread, 0 cubic tiles (params.tune)
   ViewGeom* d_geom = nullptr;   // [n]
@@ -28,9 +29,9 @@ struct tomo_plan_s {
   float2* d_prop = nullptr;     // [npairs][M]
   float2* d_tw_fwd = nullptr;   // [M]
   float2* d_tw_inv = nullptr;   // [M]
-  float2* d_tw2_fwd = nullptr;  // [M/2] twiddles of the half-size sub-transforms (M = 160, 192, 256)
-  float2* d_tw2_inv = nullptr;  // [M/2]
-  float* d_l1part = nullptr;    // [n][4] quadrant spectral bounds (M = 160, 192, 256)
+  float2* d_tw2_fwd = nullptr;  // [H] twiddles of the block sub-transforms of split sizes (M = P H)
+  float2* d_tw2_inv = nullptr;  // [H]
+  float* d_l1part = nullptr;    // [n][P^2] block spectral bounds of split sizes (FP16 planes)
   float4* d_q = nullptr;        // [n][M][M]  filtered spectra of every view
   void* d_stack = nullptr;      // [batch][M][K][M] of the plane storage type
   float* d_scale = nullptr;     // [n] FP16 plane scale per view (powers of two)
@@ -129,7 +130,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
     r->batch = std::min(b, r->n);
   }
   r->table_bytes = size_t(r->n) * sizeof(ViewGeom) + size_t(r->n) * qv + size_t(r->npairs) * r->M * 8 +
-                   2 * size_t(r->M) * 8 + size_t(r->n) * 4 + 256;
+                   4 * size_t(r->M) * 8 + size_t(r->n) * 4 * 10 + 256;
   r->work_bytes = size_t(r->n) * qv + size_t(r->batch) * sv;
   r->P = r->N + (r->N % 2 == 0 ? 1 : 0);
   if (p->fourier) {
@@ -150,7 +151,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
 std::string supported(const tomo_params* p, const Resolved& r) {
   if (!tomo::fft_supported(r.M)) {
     char b[160];
-    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: 16, 32, 48, 64, 80, 96, 128, 160, 192, 256)", r.M);
+    std::snprintf(b, sizeof b, "n_pix = %d not supported (supported: every M = 2^a 3^b 5^c in [16, 256])", r.M);
     return b;
   }
   if (p->fourier && !tomo::fourier_grid_supported(r.N)) {
@@ -394,6 +395,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   pl->npairs = r.npairs;
   pl->batch = r.batch;
   pl->P = r.P;
+  pl->split = tomo::fft_split(r.M);
   pl->p.n_pix = r.M;
   pl->p.n_planes = r.K;
   if (pl->p.i_in == 0) pl->p.i_in = 1.0;
@@ -408,7 +410,9 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   if (p->weight_mode == TOMO_RAMP_AXIS) axis_weights(dirs, r.n, geo);
   // Single-axis gather path: every v is exactly the y axis and u, d lie in the xz plane,
   // and detector rows line up with voxel rows (M - N even).
-  bool axis = ((r.M - r.N) % 2 == 0);
+  // (the LDS-fetch kernel moves 16-byte chunks: M a multiple of 4 FP32 or 8 16-bit values)
+  const int vec = p->plane_dtype == TOMO_F32 ? 4 : 8;
+  bool axis = ((r.M - r.N) % 2 == 0) && (r.M % vec == 0);
   for (int i = 0; i < r.n && axis; ++i)
     axis = geo[i].v[0] == 0.0 && geo[i].v[1] == 1.0 && geo[i].v[2] == 0.0 && geo[i].u[1] == 0.0 &&
            geo[i].d[1] == 0.0;
@@ -430,9 +434,12 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
     twf[k] = make_float2(float(std::cos(a)), float(-std::sin(a)));
     twi[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
   }
-  std::vector<float2> tw2f(r.M / 2), tw2i(r.M / 2);
-  for (int k = 0; k < r.M / 2; ++k) {
-    const double a = 2.0 * kPi * k / (r.M / 2);
+  // H-point twiddles of the P^2 block transforms of split sizes (M = P H)
+  const int split = tomo::fft_split(r.M);
+  const int hpts = split > 1 ? r.M / split : 1;
+  std::vector<float2> tw2f(hpts), tw2i(hpts);
+  for (int k = 0; k < hpts; ++k) {
+    const double a = 2.0 * kPi * k / hpts;
     tw2f[k] = make_float2(float(std::cos(a)), float(-std::sin(a)));
     tw2i[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
   }
@@ -444,9 +451,9 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       (e = dev_alloc(&pl->d_prop, prop.size())) != hipSuccess ||
       (e = dev_alloc(&pl->d_tw_fwd, size_t(r.M))) != hipSuccess ||
       (e = dev_alloc(&pl->d_tw_inv, size_t(r.M))) != hipSuccess ||
-      (e = dev_alloc(&pl->d_tw2_fwd, size_t(r.M / 2))) != hipSuccess ||
-      (e = dev_alloc(&pl->d_tw2_inv, size_t(r.M / 2))) != hipSuccess ||
-      (e = dev_alloc(&pl->d_l1part, size_t(4) * r.n)) != hipSuccess ||
+      (e = dev_alloc(&pl->d_tw2_fwd, size_t(hpts))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_tw2_inv, size_t(hpts))) != hipSuccess ||
+      (e = dev_alloc(&pl->d_l1part, size_t(split * split) * r.n)) != hipSuccess ||
       (e = dev_alloc(&pl->d_q, mm * r.n)) != hipSuccess ||
       (e = dev_alloc(reinterpret_cast<char**>(&pl->d_stack),
                      size_t(r.batch) * stack_view_bytes(r.M, r.K, p->plane_dtype))) != hipSuccess ||
@@ -474,9 +481,8 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       (e = hipMemcpyAsync(pl->d_prop, prop.data(), sizeof(float2) * prop.size(), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(pl->d_tw_fwd, twf.data(), sizeof(float2) * r.M, hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(pl->d_tw_inv, twi.data(), sizeof(float2) * r.M, hipMemcpyHostToDevice, s)) ||
-      (r.M / 2 > 0 &&
-       ((e = hipMemcpyAsync(pl->d_tw2_fwd, tw2f.data(), sizeof(float2) * (r.M / 2), hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(pl->d_tw2_inv, tw2i.data(), sizeof(float2) * (r.M / 2), hipMemcpyHostToDevice, s)))) ||
+      (e = hipMemcpyAsync(pl->d_tw2_fwd, tw2f.data(), sizeof(float2) * hpts, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(pl->d_tw2_inv, tw2i.data(), sizeof(float2) * hpts, hipMemcpyHostToDevice, s)) ||
       (e = hipMemsetAsync(pl->d_status, 0, sizeof(int), s)))
     return cleanup_fail(e, "upload");
 
@@ -563,7 +569,9 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   (void)hipFree(d_smat);
   d_wtab = nullptr;
   d_smat = nullptr;
-  if (p->tune == 2 && !pl->axis_fast) pl->grid_rows = 0;
+  // general frames: the cubic tiles when asked for, and always when stack rows cannot be
+  // fetched as 16-byte chunks (the row-tiled box kernel would gather every view from memory)
+  if ((p->tune == 2 || r.M % vec != 0) && !pl->axis_fast) pl->grid_rows = 0;
   if (p->tune == 1) {
     // time the gridding kernel with 4 and 8 voxel rows per thread on a full batch of (zeroed)
     // stacks and keep the faster; results do not depend on the choice
@@ -637,7 +645,7 @@ static tomo_status run_spectra(tomo_plan_t pl, const float* d_images, int32_t fi
   hipError_t e = timed(pl, 0, s, [&] {
     return tomo::launch_spectra(pl->M, d_images, pl->d_filt + size_t(first) * mm, pl->d_tw_fwd,
                                 pl->d_q + size_t(first) * mm, pl->d_status, 1.0 / pl->p.i_in, scale, nb, s,
-                                pl->d_tw2_fwd, pl->d_l1part + size_t(4) * first);
+                                pl->d_tw2_fwd, pl->d_l1part + size_t(pl->split * pl->split) * first);
   });
   if (e != hipSuccess) return dev_fail(pl, e, "spectra kernel");
   return TOMO_OK;
@@ -698,7 +706,7 @@ tomo_status tomo_backpropagate_noalloc(tomo_plan_t pl, const float* d_images, in
   float* scale = pl->p.plane_dtype == TOMO_F16 ? pl->d_scale + first : nullptr;
   hipError_t e = tomo::launch_spectra(pl->M, d_images, pl->d_filt + size_t(first) * mm, pl->d_tw_fwd, q,
                                       pl->d_status, 1.0 / pl->p.i_in, scale, nb, s, pl->d_tw2_fwd,
-                                      pl->d_l1part + size_t(4) * first);
+                                      pl->d_l1part + size_t(pl->split * pl->split) * first);
   if (e != hipSuccess) return fail_fixed(pl, TOMO_EDEVICE, "spectra kernel: ", hipGetErrorString(e));
   e = tomo::launch_planes(pl->M, pl->p.plane_dtype, q, pl->d_prop, pl->d_tw_inv, d_planes, pl->K, pl->npairs, nb,
                           pl->d_scale + first, s, pl->d_tw2_inv);

@@ -20,14 +20,16 @@ struct FilterArgs {
   int ewald, mode;  // mode: 0 axis ramp, 1 isotropic ramp, 2 sampling matrix
 };
 
-// Supported detector sizes of the LDS-resident 2D FFT.
+// Supported detector sizes of the LDS-resident 2D FFT (every 2,3,5-smooth M in [16, 256]),
+// threads per workgroup, and the block split P (1: direct; M = P H for M > 200).
 bool fft_supported(int M);
 int fft_threads(int M);
+int fft_split(int M);
 
 // g = ln(I/I_in) -> 2D DFT -> (G1 G, G2 G) for nb views.  filt, q: [nb][M][M] float4.
 // scale (FP16 planes only, else NULL): per-view power-of-two plane scale, [nb].
-// M = 160, 192, 256 also need the M/2-point twiddles (tw_half_fwd) and a [nb][4] scratch for
-// the quadrant bounds (l1part, FP16 only).
+// Split sizes (P > 1) also need the H-point twiddles, H = M / P (tw_half_fwd), and a
+// [nb][P^2] scratch for the block bounds (l1part, FP16 only).
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
                           float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
                           const float2* tw_half_fwd, float* l1part);

@@ -1,16 +1,9 @@
 // gfx950 kernels of the reconstruction hot path.
 //
-//   k_spectra   per view: g = ln(I/I_in) (eq. 4 left side), 2D DFT (F2 of Section 2,
-//               kernel exp(-i 2 pi r.q)), multiplied by the plan's filter table so
-//               that the Hermitian split needed below is ready:
-//                 Q1 = (1+i) F_h G / M^2,   Q2 = -(1+i) F_a G / M^2,
-//               F = C W H (eq. 11), F_h / F_a its Hermitian / anti-Hermitian parts.
-//   k_planes    per view and plane pair (j, K-1-j): the planes' spectra are
-//               Y_j = Herm[F e^{-i phi_j} G], phi_j = pi lambda z'_j q^2 (eq. 3 on the
-//               paraboloid of eqs. 8/10).  Since z'_{K-1-j} = -z'_j,
-//                 Y_j + i Y_{K-1-j} = cos(phi_j) Q1 + sin(phi_j) Q2,
-//               and one complex inverse 2D FFT yields plane j (real part) and plane
-//               K-1-j (imaginary part).  Writes the stack [view][row][plane][col].
+//   k_spectra, k_planes (fft_kernels.hpp, instantiated per size in fft_sizes_*.hip):
+//               contrast, 2D DFT and the eq. 11 filter; depth propagation (eq. 3) and
+//               the inverse 2D FFTs that write the plane stacks.  This file keeps
+//               the size table that dispatches them.
 //   k_grid_*    trilinear gather of the stacks at every voxel's view-frame position
 //               (text after eq. 11), summed over the batch's views in ascending
 //               order in registers, then one read-modify-write of V (no atomics).
@@ -22,390 +15,12 @@
 #include <cstdint>
 #include <type_traits>
 
-#include "fft.hpp"
+#include "fft_kernels.hpp"
+#include "fft_sizes.hpp"
 #include "geom.hpp"
 #include "tomo_internal.hpp"
 
 namespace tomo {
-
-// ------------------------------------------------------------------ FFT shapes
-template <int M>
-struct Shape;
-template <> struct Shape<16> : Fft2Shape<16, 4, 4> {};
-template <> struct Shape<32> : Fft2Shape<32, 8, 4> {};
-template <> struct Shape<48> : Fft2Shape<48, 12, 4> {};
-template <> struct Shape<64> : Fft2Shape<64, 16, 4> {};
-template <> struct Shape<80> : Fft2Shape<80, 20, 4> {};
-template <> struct Shape<96> : Fft2Shape<96, 24, 4> {};
-template <> struct Shape<128> : Fft2Shape<128, 16, 8> {};
-template <> struct Shape<160> : Fft2Shape<160, 40, 4> {};
-template <> struct Shape<192> : Fft2Shape<192, 48, 4> {};
-
-bool fft_supported(int M) {
-  switch (M) {
-    case 16: case 32: case 48: case 64: case 80: case 96: case 128: case 160: case 192: case 256: return true;
-    default: return false;
-  }
-}
-
-int fft_threads(int M) {
-  switch (M) {
-    case 16: return Shape<16>::T;
-    case 32: return Shape<32>::T;
-    case 48: return Shape<48>::T;
-    case 64: return Shape<64>::T;
-    case 80: return Shape<80>::T;
-    case 96: return Shape<96>::T;
-    case 128: return Shape<128>::T;
-    case 160: return Shape<160>::T;
-    case 192: return Shape<192>::T;
-    case 256: return Shape<128>::T;   // M = 2H: four H-point quadrant transforms
-    default: return 0;
-  }
-}
-
-// Exchanges through half-size LDS (real, then imaginary parts): in the plane kernels
-// where the full block would leave room for only one workgroup per CU (two fit then),
-// in the spectra kernel only where the full block would not fit in one CU's LDS.
-template <int M>
-constexpr bool kSplit = (Shape<M>::LDS_BYTES > 80 * 1024);
-template <int M>
-constexpr bool kSplitSpectra = (Shape<M>::LDS_BYTES > 160 * 1024);
-
-// ------------------------------------------------------------------ K1: spectra
-template <int M>
-__global__ __launch_bounds__(Shape<M>::T) void k_spectra(const float* __restrict__ images,
-                                                         const float4* __restrict__ filt,
-                                                         const float2* __restrict__ tw_fwd,
-                                                         float4* __restrict__ q, int* __restrict__ status,
-                                                         double inv_iin, float* __restrict__ scale) {
-  using S = Shape<M>;
-  __shared__ float2 lds[kSplitSpectra<M> ? (S::LDS_SPLIT_FLOATS + 1) / 2 : S::LDS_ELEMS];
-  __shared__ float red[S::T / 64];
-  const int t = threadIdx.x;
-  const int view = blockIdx.x;
-  const int line = t % M, r = t / M;
-  const float* img = images + size_t(view) * M * M;
-  float2 x[S::R1];
-  int bad = 0;
-#pragma unroll
-  for (int m = 0; m < S::R1; ++m) {
-    const float iv = img[(r + S::R2 * m) * M + line];
-    const bool ok = (iv > 0.0f) && (iv < INFINITY);
-    bad |= !ok;
-    // contrast in FP64, rounded once: ln(I/I_in) of an FP32 intensity near I_in
-    const double g = ok ? log(double(iv) * inv_iin) : 0.0;
-    x[m] = make_float2(float(g), 0.0f);
-  }
-  if (bad) atomicOr(status, 1);
-  if constexpr (kSplitSpectra<M>) fft2_block_split<S, false>(x, reinterpret_cast<float*>(lds), tw_fwd);
-  else fft2_block<S, false>(x, lds, tw_fwd);
-  const int sg = t % S::R2, ky = t / S::R2;
-  const size_t row = (size_t(view) * M + ky) * M;
-  float l1 = 0.0f;
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) {
-#pragma unroll
-    for (int k2 = 0; k2 < S::R2; ++k2) {
-      const int kx = sg * S::E + e + S::R1 * k2;
-      const float4 f = filt[row + kx];
-      const float2 gg = x[e * S::R2 + k2];
-      float4 o;
-      o.x = f.x * gg.x - f.y * gg.y;
-      o.y = f.x * gg.y + f.y * gg.x;
-      o.z = f.z * gg.x - f.w * gg.y;
-      o.w = f.z * gg.y + f.w * gg.x;
-      q[row + kx] = o;
-      l1 += fabsf(o.x) + fabsf(o.y) + fabsf(o.z) + fabsf(o.w);
-    }
-  }
-  if (scale) {
-    // FP16 plane storage: every plane value of this view is bounded by
-    // sum_k |cos Q1 + sin Q2| <= sum_k (|Q1| + |Q2|) <= l1; scale by the power of two that
-    // puts this bound at 2^14 (exact scaling, values stay below the FP16 maximum).
-    // Fixed-order reduction: wave sums, then the wave partials in order.
-    for (int off = 32; off > 0; off >>= 1) l1 += __shfl_xor(l1, off, 64);
-    if ((t & 63) == 0) red[t >> 6] = l1;
-    __syncthreads();
-    if (t == 0) {
-      float tot = 0.0f;
-      for (int w = 0; w < S::T / 64; ++w) tot += red[w];
-      scale[view] = tot > 0.0f ? exp2f(14.0f - ceilf(log2f(tot))) : 1.0f;
-    }
-  }
-}
-
-// ------------------------------------------------------------------ K3: planes
-// Workgroup -> (view, pair) mapping keeps all pairs of one view on one XCD
-// (workgroups are dealt to the 8 XCDs round robin), so the view's Q block is
-// fetched into one L2 only.
-
-// Plane storage types: FP32, BF16 (round to nearest even), FP16 (per-view power-of-two scale).
-template <class T>
-__device__ __forceinline__ T to_store(float v);
-template <>
-__device__ __forceinline__ float to_store<float>(float v) { return v; }
-template <>
-__device__ __forceinline__ __hip_bfloat16 to_store<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
-template <>
-__device__ __forceinline__ __half to_store<__half>(float v) { return __float2half_rn(v); }
-
-template <class T>
-__device__ __forceinline__ float from_store(T v);
-template <>
-__device__ __forceinline__ float from_store<float>(float v) { return v; }
-template <>
-__device__ __forceinline__ float from_store<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
-template <>
-__device__ __forceinline__ float from_store<__half>(__half v) { return __half2float(v); }
-
-template <int M, class OutT>
-__global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict__ q,
-                                                        const float2* __restrict__ prop,
-                                                        const float2* __restrict__ tw_inv,
-                                                        OutT* __restrict__ stack, int K, int npairs,
-                                                        int nb, const float* __restrict__ scale) {
-  using S = Shape<M>;
-  __shared__ float2 lds[kSplit<M> ? (S::LDS_SPLIT_FLOATS + 1) / 2 : S::LDS_ELEMS];
-  const int wg = blockIdx.x;
-  const int xcd = wg & 7, k = wg >> 3;
-  int view, p;
-  if (nb == 1 || nb == 2 || nb == 4) {
-    // fewer views than XCDs: view xcd % nb, its pairs dealt over the 8 / nb XCDs that share it
-    view = xcd % nb;
-    p = k * (8 / nb) + xcd / nb;
-    if (p >= npairs) return;  // whole workgroup leaves together: no barrier is skipped by part of it
-  } else {
-    view = xcd + 8 * (k / npairs);
-    p = k % npairs;
-    if (view >= nb) return;
-  }
-  const int t = threadIdx.x;
-  const int line = t % M;
-  int r_;
-  if constexpr (M % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / M);
-  else r_ = t / M;
-  const int r = r_;
-  const float4* qv = q + size_t(view) * M * M;
-  const float2* pr = prop + size_t(p) * M;
-  const float2 cx = pr[line];
-  float2 x[S::R1];
-#pragma unroll
-  for (int m = 0; m < S::R1; ++m) {
-    const int ky = r + S::R2 * m;
-    const float2 cy = pr[ky];
-    const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
-    const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
-    const float4 qq = qv[ky * M + line];
-    x[m] = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
-  }
-  // FP16 planes: per-view power-of-two scale (other storage types are not scaled), read
-  // before the transform so that its latency overlaps the spectrum loads; the empty asm
-  // keeps the compiler from sinking the read to the stores, where its wait would also
-  // wait for the last exchange's LDS reads
-  float sc = 1.0f;
-  if constexpr (std::is_same<OutT, __half>::value) {
-    sc = scale[view];
-    asm volatile("" : "+v"(sc));
-  }
-  if constexpr (kSplit<M>) fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw_inv);
-  else fft2_block<S, true>(x, lds, tw_inv);
-  const int sg = t % S::R2, y = t / S::R2;
-  const int pa = p, pb = K - 1 - p;
-  OutT* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
-  OutT* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
-#pragma unroll
-  for (int k2 = 0; k2 < S::R2; ++k2) {
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      const int xc = sg * S::E + e + S::R1 * k2;
-      rowa[xc] = to_store<OutT>(x[e * S::R2 + k2].x * sc);
-    }
-  }
-  if (pb != pa) {
-#pragma unroll
-    for (int k2 = 0; k2 < S::R2; ++k2) {
-#pragma unroll
-      for (int e = 0; e < S::E; ++e) {
-        const int xc = sg * S::E + e + S::R1 * k2;
-        rowb[xc] = to_store<OutT>(x[e * S::R2 + k2].y * sc);
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------------ M = 2H (160, 192, 256)
-// A 2H x 2H block (H = 80, 96, 128) does not fit in one CU's LDS.  One radix-2 decimation in
-// frequency on both axes splits it into four independent H x H transforms:
-//   X[2k1+p1][2k2+p2] = DFT_H(n1,n2) { w^(p1 n1 + p2 n2) sum_{a,b} (-1)^(a p1 + b p2) x[n1+Ha][n2+Hb] }
-// with w = exp(-+ i 2 pi / 2H).  Each (p1, p2) quadrant is one workgroup running the
-// H x H LDS transform; it reads its inputs from all four input quadrants and writes
-// every second output row and column.  The four workgroups of a block share an XCD.
-
-// g = ln(I/I_in) of a 2H x 2H image -> filtered spectra (Q1, Q2) at the quadrant's
-// output positions; l1part[view][quad] = partial spectral bound for the FP16 scale.
-template <int H>
-__global__ __launch_bounds__(Shape<H>::T) void k_spectra2x(const float* __restrict__ images,
-                                                          const float4* __restrict__ filt,
-                                                          const float2* __restrict__ tw256,
-                                                          const float2* __restrict__ tw128,
-                                                          float4* __restrict__ q, int* __restrict__ status,
-                                                          double inv_iin, float* __restrict__ l1part) {
-  using S = Shape<H>;
-  constexpr int M = 2 * H;
-  __shared__ float2 lds[(S::LDS_SPLIT_FLOATS + 1) / 2];
-  __shared__ float red[S::T / 64];
-  const int t = threadIdx.x;
-  const int view = blockIdx.x >> 2, quad = blockIdx.x & 3;
-  const int p1 = quad >> 1, p2 = quad & 1;
-  const int n2 = t % H;
-  int r_;   // uniform across a wave when H is a multiple of the wave size
-  if constexpr (H % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / H);
-  else r_ = t / H;
-  const int r = r_;
-  const float* img = images + size_t(view) * M * M;
-  float2 x[S::R1];
-  int bad = 0;
-#pragma unroll
-  for (int m = 0; m < S::R1; ++m) {
-    const int n1 = r + S::R2 * m;
-    float acc = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const float iv = img[(n1 + H * a) * M + n2 + H * b];
-        const bool ok = (iv > 0.0f) && (iv < INFINITY);
-        bad |= !ok;
-        const float g = ok ? float(log(double(iv) * inv_iin)) : 0.0f;
-        acc += ((a & p1) ^ (b & p2)) ? -g : g;
-      }
-    }
-    const int ti = p1 * n1 + p2 * n2;   // < 2H
-    x[m] = cscale(tw256[ti >= M ? ti - M : ti], acc);
-  }
-  if (bad) atomicOr(status, 1);
-  fft2_block_split<S, false>(x, reinterpret_cast<float*>(lds), tw128);
-  const int sg = t % S::R2, yy = t / S::R2;
-  const int ky = 2 * yy + p1;
-  const size_t row = (size_t(view) * M + ky) * M;
-  float l1 = 0.0f;
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) {
-#pragma unroll
-    for (int k2 = 0; k2 < S::R2; ++k2) {
-      const int kx = 2 * (sg * S::E + e + S::R1 * k2) + p2;
-      const float4 f = filt[row + kx];
-      const float2 gg = x[e * S::R2 + k2];
-      float4 o;
-      o.x = f.x * gg.x - f.y * gg.y;
-      o.y = f.x * gg.y + f.y * gg.x;
-      o.z = f.z * gg.x - f.w * gg.y;
-      o.w = f.z * gg.y + f.w * gg.x;
-      q[row + kx] = o;
-      l1 += fabsf(o.x) + fabsf(o.y) + fabsf(o.z) + fabsf(o.w);
-    }
-  }
-  if (l1part) {
-    for (int off = 32; off > 0; off >>= 1) l1 += __shfl_xor(l1, off, 64);
-    if ((t & 63) == 0) red[t >> 6] = l1;
-    __syncthreads();
-    if (t == 0) {
-      float tot = 0.0f;
-      for (int w = 0; w < S::T / 64; ++w) tot += red[w];
-      l1part[blockIdx.x] = tot;
-    }
-  }
-}
-
-// FP16 plane scale of each view from its four quadrant bounds (fixed summation order).
-__global__ void k_scale4(const float* __restrict__ l1part, float* __restrict__ scale, int nb) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nb) return;
-  const float tot = ((l1part[4 * v] + l1part[4 * v + 1]) + l1part[4 * v + 2]) + l1part[4 * v + 3];
-  scale[v] = tot > 0.0f ? exp2f(14.0f - ceilf(log2f(tot))) : 1.0f;
-}
-
-// Plane pairs of 2H x 2H spectra: workgroup (view, pair, quadrant).
-template <int H, class OutT>
-__global__ __launch_bounds__(Shape<H>::T) void k_planes2x(const float4* __restrict__ q,
-                                                         const float2* __restrict__ prop,
-                                                         const float2* __restrict__ tw256,
-                                                         const float2* __restrict__ tw128,
-                                                         OutT* __restrict__ stack, int K, int npairs, int nb,
-                                                         const float* __restrict__ scale) {
-  using S = Shape<H>;
-  constexpr int M = 2 * H;
-  __shared__ float2 lds[(S::LDS_SPLIT_FLOATS + 1) / 2];
-  const int wg = blockIdx.x;
-  const int xcd = wg & 7, k = wg >> 3;
-  const int per_view = npairs * 4;
-  const int view = xcd + 8 * (k / per_view);
-  const int rem = k % per_view;
-  const int p = rem >> 2, quad = rem & 3;
-  if (view >= nb) return;   // whole workgroup leaves together
-  const int p1 = quad >> 1, p2 = quad & 1;
-  const int t = threadIdx.x;
-  const int n2 = t % H;
-  int r_;   // uniform across a wave when H is a multiple of the wave size
-  if constexpr (H % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / H);
-  else r_ = t / H;
-  const int r = r_;
-  const float4* qv = q + size_t(view) * M * M;
-  const float2* pr = prop + size_t(p) * M;
-  const float2 cx0 = pr[n2], cx1 = pr[n2 + H];
-  float2 x[S::R1];
-#pragma unroll
-  for (int m = 0; m < S::R1; ++m) {
-    const int n1 = r + S::R2 * m;
-    float2 acc = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const float2 cy = pr[n1 + H * a];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const float2 cx = b ? cx1 : cx0;
-        const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
-        const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
-        const float4 qq = qv[(n1 + H * a) * M + n2 + H * b];
-        const float zr = c * qq.x + sn * qq.z, zi = c * qq.y + sn * qq.w;
-        if ((a & p1) ^ (b & p2)) {
-          acc.x -= zr;
-          acc.y -= zi;
-        } else {
-          acc.x += zr;
-          acc.y += zi;
-        }
-      }
-    }
-    const int ti = p1 * n1 + p2 * n2;   // < 2H
-    x[m] = cmul(acc, tw256[ti >= M ? ti - M : ti]);
-  }
-  // FP16 planes: per-view power-of-two scale (other storage types are not scaled), read
-  // before the transform so that its latency overlaps the spectrum loads; the empty asm
-  // keeps the compiler from sinking the read to the stores, where its wait would also
-  // wait for the last exchange's LDS reads
-  float sc = 1.0f;
-  if constexpr (std::is_same<OutT, __half>::value) {
-    sc = scale[view];
-    asm volatile("" : "+v"(sc));
-  }
-  fft2_block_split<S, true>(x, reinterpret_cast<float*>(lds), tw128);
-  const int sg = t % S::R2, yy = t / S::R2;
-  const int y = 2 * yy + p1;
-  const int pa = p, pb = K - 1 - p;
-  OutT* rowa = stack + ((size_t(view) * M + y) * K + pa) * M;
-  OutT* rowb = stack + ((size_t(view) * M + y) * K + pb) * M;
-#pragma unroll
-  for (int k2 = 0; k2 < S::R2; ++k2) {
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      const int xc = 2 * (sg * S::E + e + S::R1 * k2) + p2;
-      rowa[xc] = to_store<OutT>(x[e * S::R2 + k2].x * sc);
-      if (pb != pa) rowb[xc] = to_store<OutT>(x[e * S::R2 + k2].y * sc);
-    }
-  }
-}
 
 // ------------------------------------------------------------------ inspection
 __global__ void k_spectra_out(const float4* __restrict__ q, float2* __restrict__ out, size_t count,
@@ -1160,98 +775,51 @@ __global__ void k_sampling_weights(FilterArgs fa, const ViewGeom* __restrict__ g
 }
 
 // ------------------------------------------------------------------ launchers
-template <int M>
-static hipError_t spectra_impl(const float* images, const float4* filt, const float2* tw, float4* q,
-                               int* status, double inv_iin, float* scale, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(k_spectra<M>, dim3(nb), dim3(Shape<M>::T), 0, s, images, filt, tw, q, status,
-                     inv_iin, scale);
-  return hipGetLastError();
+// Size table of the spectra / plane kernels: one group per translation unit.
+const FftSize* fft_size(int M) {
+  struct Group {
+    const FftSize* sizes;
+    int count;
+  };
+  static const Group groups[] = {
+      {kFftSizesA, kFftSizesACount}, {kFftSizesB, kFftSizesBCount}, {kFftSizesC, kFftSizesCCount},
+      {kFftSizesD, kFftSizesDCount}, {kFftSizesE, kFftSizesECount}, {kFftSizesF, kFftSizesFCount},
+      {kFftSizesG, kFftSizesGCount}, {kFftSizesH, kFftSizesHCount}, {kFftSizesI, kFftSizesICount},
+      {kFftSizesJ, kFftSizesJCount}};
+  for (const Group& g : groups)
+    for (int i = 0; i < g.count; ++i)
+      if (g.sizes[i].M == M) return &g.sizes[i];
+  return nullptr;
 }
 
-template <int M, class OutT>
-static hipError_t planes_impl(const float4* q, const float2* prop, const float2* tw, void* stack, int K,
-                              int npairs, int nb, const float* scale, hipStream_t s) {
-  // one workgroup per (view, pair), eight XCD columns; the kernel's mapping for nb = 1, 2, 4
-  // spreads each view's pairs over 8 / nb XCDs
-  const int reps = (nb == 1 || nb == 2 || nb == 4) ? 8 / nb : 0;
-  const int rows = reps ? (npairs + reps - 1) / reps : npairs * ((nb + 7) / 8);
-  hipLaunchKernelGGL((k_planes<M, OutT>), dim3(8 * rows), dim3(Shape<M>::T), 0, s, q, prop, tw,
-                     static_cast<OutT*>(stack), K, npairs, nb, scale);
-  return hipGetLastError();
+bool fft_supported(int M) { return fft_size(M) != nullptr; }
+
+int fft_threads(int M) {
+  const FftSize* f = fft_size(M);
+  return f ? f->threads : 0;
 }
 
-template <int M>
-static hipError_t planes_dtype(int dtype, const float4* q, const float2* prop, const float2* tw, void* stack,
-                               int K, int npairs, int nb, const float* scale, hipStream_t s) {
-  switch (dtype) {
-    case 0: return planes_impl<M, float>(q, prop, tw, stack, K, npairs, nb, nullptr, s);
-    case 1: return planes_impl<M, __hip_bfloat16>(q, prop, tw, stack, K, npairs, nb, nullptr, s);
-    case 2: return scale ? planes_impl<M, __half>(q, prop, tw, stack, K, npairs, nb, scale, s) : hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-  }
+int fft_split(int M) {
+  const FftSize* f = fft_size(M);
+  return f ? f->P : 0;
 }
-
-#define TOMO_DISPATCH_M(M_, CALL)                       \
-  switch (M_) {                                          \
-    case 16: return CALL(16);                            \
-    case 32: return CALL(32);                            \
-    case 48: return CALL(48);                            \
-    case 64: return CALL(64);                            \
-    case 80: return CALL(80);                            \
-    case 96: return CALL(96);                            \
-    case 128: return CALL(128);                          \
-    case 160: return CALL(160);                          \
-    case 192: return CALL(192);                          \
-    default: return hipErrorInvalidValue;                \
-  }
 
 hipError_t launch_spectra(int M, const float* images, const float4* filt, const float2* tw_fwd,
                           float4* q, int* status, double inv_iin, float* scale, int nb, hipStream_t s,
                           const float2* tw_half_fwd, float* l1part) {
   if (nb <= 0) return hipSuccess;
-  if (M == 256) {
-    hipLaunchKernelGGL(k_spectra2x<128>, dim3(4 * nb), dim3(Shape<128>::T), 0, s, images, filt, tw_fwd,
-                       tw_half_fwd, q, status, inv_iin, scale ? l1part : nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !scale) return e;
-    hipLaunchKernelGGL(k_scale4, dim3((nb + 255) / 256), dim3(256), 0, s, l1part, scale, nb);
-    return hipGetLastError();
-  }
-#define CALL(MM) spectra_impl<MM>(images, filt, tw_fwd, q, status, inv_iin, scale, nb, s)
-  TOMO_DISPATCH_M(M, CALL)
-#undef CALL
-}
-
-template <int H, class OutT>
-static hipError_t planes2x_impl(const float4* q, const float2* prop, const float2* tw256, const float2* tw128,
-                                void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s) {
-  const int nb8 = (nb + 7) / 8;
-  hipLaunchKernelGGL((k_planes2x<H, OutT>), dim3(8 * 4 * npairs * nb8), dim3(Shape<H>::T), 0, s, q, prop, tw256,
-                     tw128, static_cast<OutT*>(stack), K, npairs, nb, scale);
-  return hipGetLastError();
-}
-
-template <int H>
-static hipError_t planes2x_dtype(int dtype, const float4* q, const float2* prop, const float2* tw256,
-                                 const float2* tw128, void* stack, int K, int npairs, int nb, const float* scale,
-                                 hipStream_t s) {
-  switch (dtype) {
-    case 0: return planes2x_impl<H, float>(q, prop, tw256, tw128, stack, K, npairs, nb, nullptr, s);
-    case 1: return planes2x_impl<H, __hip_bfloat16>(q, prop, tw256, tw128, stack, K, npairs, nb, nullptr, s);
-    case 2: return scale ? planes2x_impl<H, __half>(q, prop, tw256, tw128, stack, K, npairs, nb, scale, s)
-                         : hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-  }
+  const FftSize* f = fft_size(M);
+  if (!f) return hipErrorInvalidValue;
+  return f->spectra(SpectraLaunch{images, filt, tw_fwd, tw_half_fwd, q, status, inv_iin, scale, l1part, nb, s});
 }
 
 hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, const float2* tw_inv,
                          void* stack, int K, int npairs, int nb, const float* scale, hipStream_t s,
                          const float2* tw_half_inv) {
   if (nb <= 0) return hipSuccess;
-  if (M == 256) return planes2x_dtype<128>(dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s);
-#define CALL(MM) planes_dtype<MM>(dtype, q, prop, tw_inv, stack, K, npairs, nb, scale, s)
-  TOMO_DISPATCH_M(M, CALL)
-#undef CALL
+  const FftSize* f = fft_size(M);
+  if (!f) return hipErrorInvalidValue;
+  return f->planes(PlanesLaunch{dtype, q, prop, tw_inv, tw_half_inv, stack, K, npairs, nb, scale, s});
 }
 
 template <int kYB, class InT>

@@ -216,5 +216,37 @@ def make(name: str) -> Problem:
     raise KeyError(name)
 
 
+def smooth_sizes(lo: int = 16, hi: int = 256) -> list:
+    """Every M = 2^a 3^b 5^c in [lo, hi]: the detector sizes the library supports."""
+    out = []
+    for m in range(lo, hi + 1):
+        r = m
+        for f in (2, 3, 5):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            out.append(m)
+    return out
+
+
+def size_problem(m: int) -> Problem:
+    """A small problem on an M-pixel detector: a volume of edge N = min(M, 40) or one less
+    (so that both parities of M - N occur), 12 depth planes, 3 views -- single-axis with the
+    axis ramp for even M, directions on the sphere with the isotropic ramp for odd M."""
+    dx = 1e-10
+    n_vox = min(m, 40) - (m % 4 == 2)
+    n = 3
+    if m % 2 == 0:
+        dirs = scan.single_axis(n, 180.0, offset_deg=5.0 + m % 7)
+        mode = "ramp_axis"
+    else:
+        dirs = scan.uniform_sphere(300 + m, n)
+        mode = "ramp_iso"
+    dist = np.full(n, 60e-10)
+    lam, sig = 0.05e-10, 0.1
+    imgs = _born(300 + m, n_vox, m, dx, lam, dirs, dist, sig, count=16)
+    return Problem(f"size{m}", n_vox, m, 12, dx, lam, sig, 1e-3, 1, mode, dirs, dist, imgs)
+
+
 SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32",
          "m256", "m256sph", "m160", "m192", "narrow48", "iin32", "m256iin", "pole24", "m128"]

@@ -88,9 +88,14 @@ def test_plan_rejects_ramp_axis_off_axis_direction():
     assert st == tomo.EINVAL and "y axis" in err
 
 
-def test_plan_unsupported_sizes_and_bad_dtype():
-    st, err = _plan_status(_params(n_pix=100))
+@pytest.mark.parametrize("m", [14, 98, 112, 264, 7 * 32])
+def test_plan_refuses_detector_sizes_outside_the_contract(m):
+    """Supported: every M = 2^a 3^b 5^c in [16, 256]; others are refused before any device work."""
+    st, err = _plan_status(_params(n_pix=m))
     assert st == tomo.EUNSUPPORTED and "n_pix" in err
+
+
+def test_plan_refuses_bad_plane_dtype():
     st, err = _plan_status(_params(plane_dtype=7))
     assert st == tomo.EINVAL and "plane_dtype" in err
 
