@@ -104,10 +104,13 @@ typedef struct {
                              (16 (N+1)^3 bytes) */
   int32_t tune;           /* 1: time the gridding variants on a batch of stacks at plan time
                              and keep the fastest: 4 or 8 voxel rows per thread, and for
-                             views in general frames also 8x8x8 cubic tiles; 0: 8 rows;
-                             2: cubic tiles for general frames (8 rows for single-axis plans).
-                             Single-axis plans give identical results either way; for other
-                             frames the choice moves only the FP32 rounding */
+                             views in general frames also 8x8x8 cubic tiles and the near-axis
+                             box kernel (footprints of 16 x 4 x 16 or 16 x 2 x 16 voxel tiles
+                             fetched straight into LDS); 0: 8 rows; 2: cubic tiles for general
+                             frames; 3: the near-axis box kernel (4 rows) for general frames
+                             (2 and 3 keep 8 rows for single-axis plans).  Single-axis plans
+                             give identical results either way; for other frames the choice
+                             moves only the FP32 rounding */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
                                  when plan tables + workspace would exceed it */
 } tomo_params;
@@ -259,7 +262,8 @@ tomo_status tomo_batch_sync(tomo_batch_t batch, void* stream);
 const char* tomo_batch_error(tomo_batch_t batch);
 tomo_status tomo_batch_destroy(tomo_batch_t batch);
 
-/* Gridding variant of the plan: voxel rows per thread (4 or 8), or 0 for cubic tiles (see tune). */
+/* Gridding variant of the plan: voxel rows per thread (4 or 8) of the row-tiled kernels, 0 for
+ * cubic tiles, -4 or -2 for the near-axis box kernel with 4 or 2 rows per thread (see tune). */
 int32_t tomo_grid_rows(tomo_plan_t plan);
 
 /* Non-zero entries of the plan's Fourier-space gridding operator (0 unless fourier = 1). */

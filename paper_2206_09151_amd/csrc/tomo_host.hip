@@ -107,7 +107,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
   if (p->angle_batch < 0) return "angle_batch must be >= 0";
   if (p->fourier < 0 || p->fourier > 2) return "fourier must be 0, 1 or 2";
-  if (p->tune < 0 || p->tune > 2) return "tune must be 0, 1 or 2";
+  if (p->tune < 0 || p->tune > 3) return "tune must be 0, 1, 2 or 3";
   r->N = p->n_vox;
   r->M = p->n_pix ? p->n_pix : p->n_vox;
   if (p->n_pix < 0) return "n_pix must be >= 0";
@@ -572,6 +572,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   // general frames: the cubic tiles when asked for, and always when stack rows cannot be
   // fetched as 16-byte chunks (the row-tiled box kernel would gather every view from memory)
   if ((p->tune == 2 || r.M % vec != 0) && !pl->axis_fast) pl->grid_rows = 0;
+  if (p->tune == 3 && !pl->axis_fast && r.M % vec == 0) pl->grid_rows = tomo::kGridTilt4;
   if (p->tune == 1) {
     // time the gridding kernel with 4 and 8 voxel rows per thread on a full batch of (zeroed)
     // stacks and keep the faster; results do not depend on the choice
@@ -591,8 +592,11 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
         (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(pl->d_scale), 0x3f800000u, size_t(r.n), s)))
       return tune_fail(e);
     float best = 0.0f;
-    for (int rows : {8, 4, 0}) {
-      if (rows == 0 && pl->axis_fast) continue;   // the cubic tiles serve general frames only
+    for (int rows : {8, 4, 0, tomo::kGridTilt4, tomo::kGridTilt2}) {
+      // the cubic tiles and the near-axis box serve general frames only; the row-tiled and
+      // near-axis kernels need stack rows of whole 16-byte chunks
+      if (rows <= 0 && pl->axis_fast) continue;
+      if (rows != 0 && r.M % vec != 0) continue;
       float tot = 0.0f;
       for (int rep = 0; rep < 4; ++rep) {
         if ((e = hipEventRecord(ea, s)) ||

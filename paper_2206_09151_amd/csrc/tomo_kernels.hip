@@ -489,6 +489,242 @@ __global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
   }
 }
 
+// Near-axis general frames (single-axis scans with a tilt, directions close to the rotation
+// axis's normal plane): per view, the bounding box of the workgroup's 16 (x) x YB (y) x 16 (z)
+// voxel tile in (row, plane, column) coordinates -- BR = YB + 4 detector rows x 24 planes x
+// BOXW columns -- is fetched straight into LDS by buffer loads with the LDS destination, as in
+// k_grid_axis_dma: chunk-linear boxes, chunks outside the stack zero-filled by the hardware, two
+// boxes alternating so that view n + 1 is in flight while view n is interpolated (trilinear:
+// eight LDS taps per voxel row).  Per view the box origin and whether the footprint fits are
+// computed one view per lane (FP64, from the tile corners) and read out with readlane; a view
+// whose footprint does not fit is gathered for that tile straight from global memory.
+template <int YB, class InT>
+__global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ stack,
+                                                       const ViewGeom* __restrict__ geom,
+                                                       const float* __restrict__ scale,
+                                                       float* __restrict__ vol, int N, int M, int K, int nb,
+                                                       int accumulate, int flat, double hm, double hk) {
+  constexpr int VEC = DmaBox<InT>::VEC, BOXW = DmaBox<InT>::BOXW, QN = BOXW / VEC;
+  constexpr int ES = int(sizeof(InT));                  // bytes per stored value
+  constexpr int BR = YB + 4, BH = AX_BOXH;              // rows and planes staged per view
+  constexpr int PITCH = BOXW * ES / 4;                  // dwords per staged (row, plane)
+  constexpr int NE = BR * BH * QN;                      // chunks per staged view
+  constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
+  constexpr int PAD = ES == 2 ? 4 : 0;                  // 16-bit tap pairs may read one dword past a row
+  __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + PAD];
+  __shared__ __attribute__((aligned(16))) unsigned box1[NE * 4 + PAD];
+  const int ntx = (N + GT - 1) / GT;
+  const int tiles = ntx * ntx;
+  const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
+  const int yblk = xcd + 8 * (k / tiles), tile = k % tiles;
+  const int y0 = yblk * YB;
+  if (y0 >= N) return;                                  // uniform
+  const int tx0 = (tile % ntx) * GT, tz0 = (tile / ntx) * GT;
+  const int ix = tx0 + (threadIdx.x % GT);
+  const int iz = tz0 + (threadIdx.x / GT);
+  const bool live = ix < N && iz < N;
+  const double c = 0.5 * (N - 1);
+  const double rx = ix - c, rz = iz - c, ry0 = y0 - c;
+  const size_t view_sz = size_t(K) * M * M;
+  const int wbase = (threadIdx.x & ~63) * 4;            // this wave's first dword in a box, per load
+  const int lane = threadIdx.x & 63;
+
+  // box origin (column rounded down to a 16-byte chunk) and fit of view n, one view per lane
+  int obase = -64, lane_c0 = 0, lane_r0 = 0, lane_p0 = 0, lane_fit = 0;
+  auto origin = [&](int n, int& c0, int& r0, int& p0) -> bool {
+    if (n >= obase + 64) {
+      obase = n;
+      const int v = n + lane;
+      int cc = 0, rr = 0, pp = 0, ft = 0;
+      if (v < nb) {
+        const int t0 = opaque(tx0), z0 = opaque(tz0);
+        const double lo[3] = {t0 - c, ry0, z0 - c};
+        const double hi[3] = {t0 + GT - 1 - c, ry0 + (YB - 1), z0 + GT - 1 - c};
+        const ViewGeom& g = geom[v];
+        double cmin = hm, cmax = hm, rmin = hm, rmax = hm, pmin = hk, pmax = hk;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cmin += fmin(g.u[a] * lo[a], g.u[a] * hi[a]);
+          cmax += fmax(g.u[a] * lo[a], g.u[a] * hi[a]);
+          rmin += fmin(g.v[a] * lo[a], g.v[a] * hi[a]);
+          rmax += fmax(g.v[a] * lo[a], g.v[a] * hi[a]);
+          pmin += fmin(g.d[a] * lo[a], g.d[a] * hi[a]);
+          pmax += fmax(g.d[a] * lo[a], g.d[a] * hi[a]);
+        }
+        cc = int(floor(cmin)) & ~(VEC - 1);
+        rr = int(floor(rmin));
+        pp = flat ? 0 : int(floor(pmin));
+        // taps reach floor(max) + 1; one slot of slack for the FP32 rounding of the local coordinates
+        ft = (int(floor(cmax)) + 2 - cc < BOXW) && (int(floor(rmax)) + 2 - rr < BR) &&
+             (flat || int(floor(pmax)) + 2 - pp < BH);
+      }
+      lane_c0 = cc;
+      lane_r0 = rr;
+      lane_p0 = pp;
+      lane_fit = ft;
+    }
+    c0 = __builtin_amdgcn_readlane(lane_c0, n - obase);
+    r0 = __builtin_amdgcn_readlane(lane_r0, n - obase);
+    p0 = __builtin_amdgcn_readlane(lane_p0, n - obase);
+    return __builtin_amdgcn_readlane(lane_fit, n - obase) != 0;
+  };
+  // per chunk slot: byte offset from the box origin, and its (row, plane, column) in the box
+  // (the host launches this kernel only for M a multiple of VEC and views below 2^31 bytes)
+  unsigned cfo[PER];
+  int cj[PER], cpl[PER], cq[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int q = e % QN, pl = (e / QN) % BH, j = e / (QN * BH);
+    cq[i] = VEC * q;
+    cpl[i] = pl;
+    cj[i] = e < NE ? j : -1;
+    cfo[i] = unsigned((j * K + pl) * M + VEC * q) * unsigned(ES);
+  }
+  auto has = [&](int i) { return NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE; };
+  auto load = [&](int n, int c0, int r0, int p0, unsigned* dst) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<InT*>(stack + size_t(n) * view_sz), short(0), int(view_sz * ES), 0x00020000);
+    if (r0 >= 0 && r0 + BR <= M && p0 >= 0 && p0 + BH <= K && c0 >= 0 && c0 + BOXW <= M) {
+      const int so = ((r0 * K + p0) * M + c0) * ES;
+#pragma unroll
+      for (int i = 0; i < PER; ++i)
+        if (has(i))
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 1024 * i + wbase), 16, int(cfo[i]), so,
+                                                   0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (has(i)) {
+          const int row = r0 + cj[i], pp = p0 + cpl[i], cc = c0 + cq[i];
+          const bool ok = cj[i] >= 0 && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) &&
+                          unsigned(cc) < unsigned(M);
+          const unsigned off = ok ? unsigned((row * K + pp) * M + cc) * unsigned(ES) : kOutOfRange;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 1024 * i + wbase), 16, int(off), 0,
+                                                   0, 0);
+        }
+      }
+    }
+  };
+
+  float acc[YB];
+#pragma unroll
+  for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
+  int oc0 = 0, or0 = 0, op0 = 0, oc1 = 0, or1 = 0, op1 = 0;   // origins of the views in each buffer
+  bool of0 = false, of1 = false;                              // their footprints fit
+  auto step = [&](unsigned* bx, int& cb, int& rb, int& pb, bool& fb, unsigned* other, int& co, int& ro, int& po,
+                  bool& fo, int n) {
+    if (n >= nb) return;                                // uniform
+    __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (n + 1 < nb) {
+      fo = origin(n + 1, co, ro, po);
+      if (fo) load(n + 1, co, ro, po, other);
+    }
+    if (!live) return;
+    const ViewGeom& g = geom[n];
+    float inv = 1.0f;
+    if constexpr (std::is_same<InT, __half>::value) inv = 1.0f / scale[n];   // exact: a power of two
+    // flat (one plane): a zero depth direction and hk = 0 put every tap on plane 0 with the
+    // second plane's (zero-filled) taps at weight 0
+    const double d0 = flat ? 0.0 : g.d[0], d1 = flat ? 0.0 : g.d[1], d2 = flat ? 0.0 : g.d[2];
+    if (fb) {
+      // box-local coordinates of the first voxel row in FP64, rounded once; the other rows
+      // step by (u_y, v_y, d_y) in FP32 (|local| < 32: error ~1e-6 voxel)
+      const float lc0 = float(g.u[0] * rx + g.u[1] * ry0 + g.u[2] * rz + (hm - cb));
+      const float lr0 = float(g.v[0] * rx + g.v[1] * ry0 + g.v[2] * rz + (hm - rb));
+      const float lp0 = float(d0 * rx + d1 * ry0 + d2 * rz + (hk - pb));
+      const float uy = float(g.u[1]), vy = float(g.v[1]), dy = float(d1);
+#pragma unroll
+      for (int j = 0; j < YB; ++j) {
+        // fmax guards a rounding-level dip below the box origin; non-negative: truncation floors
+        const float fc = fmaxf(fmaf(float(j), uy, lc0), 0.0f);
+        const float fr = fmaxf(fmaf(float(j), vy, lr0), 0.0f);
+        const float fp = fmaxf(fmaf(float(j), dy, lp0), 0.0f);
+        const int lc = int(fc), lr = int(fr), lp = int(fp);
+        const float tc = fc - float(lc), tr = fr - float(lr), tp = fp - float(lp);
+        const int o = (lr * BH + lp) * PITCH;           // dwords to (row lr, plane lp)
+        float t[8];                                     // (row, plane, col) = (lr + a, lp + b, lc + e) at 4a + 2b + e
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+          const int oo = o + (ab >> 1) * BH * PITCH + (ab & 1) * PITCH;
+          if constexpr (ES == 4) {
+            const float* r0 = reinterpret_cast<const float*>(bx) + oo + lc;
+            t[2 * ab] = r0[0];
+            t[2 * ab + 1] = r0[1];
+          } else {
+            const unsigned* r0 = bx + oo + (lc >> 1);
+            const unsigned pr = __builtin_amdgcn_alignbit(r0[1], r0[0], unsigned(lc & 1) * 16u);
+            if constexpr (std::is_same<InT, __half>::value) {
+              t[2 * ab] = __half2float(__ushort_as_half((unsigned short)(pr & 0xffffu)));
+              t[2 * ab + 1] = __half2float(__ushort_as_half((unsigned short)(pr >> 16)));
+            } else {
+              t[2 * ab] = __uint_as_float(pr << 16);
+              t[2 * ab + 1] = __uint_as_float(pr & 0xffff0000u);
+            }
+          }
+        }
+        const float v00 = fmaf(tc, t[1] - t[0], t[0]), v01 = fmaf(tc, t[3] - t[2], t[2]);
+        const float v10 = fmaf(tc, t[5] - t[4], t[4]), v11 = fmaf(tc, t[7] - t[6], t[6]);
+        const float w0 = fmaf(tp, v01 - v00, v00), w1 = fmaf(tp, v11 - v10, v10);
+        acc[j] = fmaf(inv, fmaf(tr, w1 - w0, w0), acc[j]);
+      }
+    } else {
+      const InT* base = stack + size_t(n) * view_sz;
+      // footprint too large for the box: one voxel row per iteration from global memory
+#pragma unroll 1
+      for (int j = 0; j < YB; ++j) {
+        const double ry = ry0 + j;
+        const double fc = g.u[0] * rx + g.u[1] * ry + g.u[2] * rz + hm;
+        const double fr = g.v[0] * rx + g.v[1] * ry + g.v[2] * rz + hm;
+        const double fp = d0 * rx + d1 * ry + d2 * rz + hk;
+        const double fc0 = floor(fc), fr0 = floor(fr), fp0 = floor(fp);
+        const float tc = float(fc - fc0), tr = float(fr - fr0), tp = float(fp - fp0);
+        const int c0i = int(fc0), r0i = int(fr0), p0i = int(fp0);
+        const float wc0 = (unsigned(c0i) < unsigned(M)) ? 1.0f - tc : 0.0f;
+        const float wc1 = (unsigned(c0i + 1) < unsigned(M)) ? tc : 0.0f;
+        const float wr0 = (unsigned(r0i) < unsigned(M)) ? 1.0f - tr : 0.0f;
+        const float wr1 = (unsigned(r0i + 1) < unsigned(M)) ? tr : 0.0f;
+        const float wp0 = (unsigned(p0i) < unsigned(K)) ? 1.0f - tp : 0.0f;
+        const float wp1 = (unsigned(p0i + 1) < unsigned(K)) ? tp : 0.0f;
+        const int c0c = min(max(c0i, 0), M - 1), c1c = min(max(c0i + 1, 0), M - 1);
+        const int r0c = min(max(r0i, 0), M - 1), r1c = min(max(r0i + 1, 0), M - 1);
+        const int p0c = min(max(p0i, 0), K - 1), p1c = min(max(p0i + 1, 0), K - 1);
+        const InT* a0 = base + (size_t(r0c) * K + p0c) * M;
+        const InT* a1 = base + (size_t(r0c) * K + p1c) * M;
+        const InT* b0 = base + (size_t(r1c) * K + p0c) * M;
+        const InT* b1 = base + (size_t(r1c) * K + p1c) * M;
+        const float v0 = wc0 * from_store<InT>(a0[c0c]) + wc1 * from_store<InT>(a0[c1c]);
+        const float v1 = wc0 * from_store<InT>(a1[c0c]) + wc1 * from_store<InT>(a1[c1c]);
+        const float v2 = wc0 * from_store<InT>(b0[c0c]) + wc1 * from_store<InT>(b0[c1c]);
+        const float v3 = wc0 * from_store<InT>(b1[c0c]) + wc1 * from_store<InT>(b1[c1c]);
+        const float add = inv * (wr0 * (wp0 * v0 + wp1 * v1) + wr1 * (wp0 * v2 + wp1 * v3));
+#pragma unroll
+        for (int jj = 0; jj < YB; ++jj) acc[jj] += (jj == j) ? add : 0.0f;
+      }
+    }
+  };
+  if (nb > 0) {
+    of0 = origin(0, oc0, or0, op0);
+    if (of0) load(0, oc0, or0, op0, box0);
+  }
+  for (int n0 = 0; n0 < nb; n0 += 2) {
+    step(box0, oc0, or0, op0, of0, box1, oc1, or1, op1, of1, n0);
+    step(box1, oc1, or1, op1, of1, box0, oc0, or0, op0, of0, n0 + 1);
+  }
+  if (!live) return;
+#pragma unroll
+  for (int j = 0; j < YB; ++j) {
+    const int iy = y0 + j;
+    if (iy < N) {
+      float* dst = vol + (size_t(iz) * N + iy) * N + ix;
+      *dst = accumulate ? *dst + acc[j] : acc[j];
+    }
+  }
+}
+
 // General view frames, cubic tiles: 8 x 8 x 8 voxels, two per thread (iz and iz + 4).
 // The voxel centres of a cube of edge 8 span at most 7 (|a_x| + |a_y| + |a_z|) <= 7 sqrt(3)
 // < 12.2 along any unit vector a, so with the taps and the floor of the origin a box of
@@ -867,8 +1103,35 @@ static hipError_t grid_cube_impl(const void* stack, const ViewGeom* geom, const 
   return hipGetLastError();
 }
 
+template <int YB, class InT>
+static hipError_t grid_tilt_impl(const void* stack, const ViewGeom* geom, const float* scale, float* vol, int N,
+                                 int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
+  if (M % DmaBox<InT>::VEC != 0 || size_t(K) * M * M * sizeof(InT) > size_t(0x7fffffff)) return hipErrorInvalidValue;
+  const int ntx = (N + GT - 1) / GT;
+  const int yblocks8 = ((N + YB - 1) / YB + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_grid_tilt_dma<YB, InT>), dim3(unsigned(ntx * ntx * yblocks8)), dim3(256), 0, s,
+                     static_cast<const InT*>(stack), geom, scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1),
+                     flat ? 0.0 : 0.5 * (K - 1));
+  return hipGetLastError();
+}
+
+template <int YB>
+static hipError_t grid_tilt_dtype(int dtype, const void* stack, const ViewGeom* geom, const float* scale, float* vol,
+                                  int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s) {
+  switch (dtype) {
+    case 0: return grid_tilt_impl<YB, float>(stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+    case 1: return grid_tilt_impl<YB, __hip_bfloat16>(stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);
+    case 2: return grid_tilt_impl<YB, __half>(stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
                        float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s, int rows) {
+  if (rows == kGridTilt4 && !axis_fast)
+    return grid_tilt_dtype<4>(dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+  if (rows == kGridTilt2 && !axis_fast)
+    return grid_tilt_dtype<2>(dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   if (rows == 0 && !axis_fast) {
     switch (dtype) {
       case 0: return grid_cube_impl<float>(stack, geom, nullptr, vol, N, M, K, nb, accumulate, flat, s);

@@ -77,3 +77,20 @@ def test_cubic_tile_gridding_16bit(name, dtype):
     e16 = _rel(v.cpu().numpy().astype(np.float64), ref)
     print(f"cubic tiles {name} dtype={dtype}: rel-L2 vs FP64 = {e16:.3e}")
     assert e16 < BOUND[dtype], e16
+
+
+@pytest.mark.parametrize("name", ["sampling32", "m256iin", "sphere45"])
+@pytest.mark.parametrize("dtype", [1, 2], ids=["bf16", "fp16"])
+def test_near_axis_box_gridding_16bit(name, dtype):
+    """The near-axis box kernel (tune = 3) with 16-bit stacks (tap pairs from packed 16-bit
+    values in LDS; the FP16 scale folded into the sum)."""
+    from paper_2206_09151_amd import tomo
+    pb = _problems.make(name)
+    plan = tomo.Plan(pb.params(tune=3, plane_dtype=dtype), pb.dirs, pb.dist, vaxes=pb.vaxes)
+    assert plan.grid_rows == -4
+    v = torch.empty((pb.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+    plan.reconstruct(torch.from_numpy(pb.images).to("cuda:0"), v)
+    ref = oracle.reconstruct(pb.images.astype(np.float64), pb.dirs, pb.dist, pb.oracle_geometry(), vaxes=pb.vaxes)
+    e16 = _rel(v.cpu().numpy().astype(np.float64), ref)
+    print(f"near-axis box {name} dtype={dtype}: rel-L2 vs FP64 = {e16:.3e}")
+    assert e16 < BOUND[dtype], e16
