@@ -93,14 +93,20 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
-def kernel_source_hash() -> str:
-    """Hash of the kernel sources' code: // comments, trailing blanks and empty lines are
-    left out, so that editing a comment does not orphan the stored counter summaries."""
-    h = hashlib.sha256()
+def kernel_source_hash(method: str = "realspace") -> str:
+    """Hash of the code of the kernel sources a method runs (real-space: the FFT, spectra,
+    plane and gridding kernels; fourier: the FFT header and the Fourier-space kernels): //
+    comments, trailing blanks and empty lines are left out, so that editing a comment does not
+    orphan the stored counter summaries."""
     csrc = os.path.join(ROOT, "paper_2206_09151_amd", "csrc")
-    sizes = sorted(f for f in os.listdir(csrc) if f.startswith("fft_sizes"))
-    for f in ["fft.hpp", "fft_kernels.hpp", "geom.hpp", "tomo_kernels.hip", "fourier_kernels.hip"] + sizes:
-        with open(os.path.join(ROOT, "paper_2206_09151_amd", "csrc", f), encoding="utf-8") as fh:
+    if method == "fourier":
+        files = ["fft.hpp", "geom.hpp", "fourier_kernels.hip"]
+    else:
+        files = ["fft.hpp", "fft_kernels.hpp", "geom.hpp", "tomo_kernels.hip"] + \
+            sorted(f for f in os.listdir(csrc) if f.startswith("fft_sizes"))
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
             for line in fh:
                 code = line.split("//", 1)[0].rstrip()
                 if code:
@@ -315,7 +321,7 @@ def main():
                              "algorithmic_bytes_per_launch": per_launch,
                              "GBps": per_launch / (avg_ms * 1e-3) / 1e9}
         dom = max(kernels, key=lambda kk: kernels[kk]["ms_per_step"])
-        src_hash = kernel_source_hash()
+        src_hash = kernel_source_hash("fourier" if fourier else "realspace")
         achieved = kernels[dom]["GBps"]
         sb = 4 if args.plane_dtype == "f32" else 2
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -449,13 +455,19 @@ def run_batch(args):
     recorded graph: a step is one launch of all jobs; value = total N^3 n of the jobs
     per second.  Per-kernel figures come from one eager pass over the jobs with the
     library's event timing."""
-    import multiprocessing as mp
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
     from synth import workloads
     jobs = workloads.batch_jobs()
     t0 = time.time()
-    # inputs are drawn before anything touches the GPU (worker processes are plain CPU work)
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-        data = pool.map(_make_job, jobs)
+    # inputs are drawn on host threads (numpy releases the interpreter lock in its array work),
+    # so that the bench stays one process, also under a profiler
+    data = []
+    with threadpool_limits(1), ThreadPoolExecutor(host_threads()) as pool:
+        for i in range(0, len(jobs), 16):
+            data += list(pool.map(_make_job, jobs[i:i + 16]))
+            print(f"[bench] batch64: {len(data)}/{len(jobs)} jobs generated in {time.time() - t0:.0f}s",
+                  file=sys.stderr, flush=True)
     print(f"[bench] batch64: {len(jobs)} jobs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     import torch
     from paper_2206_09151_amd import tomo
@@ -510,7 +522,7 @@ def run_batch(args):
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "note": "eager pass over the 64 jobs with library event timing (the graph holds no events)",
-                    "kernel_source_hash": kernel_source_hash()}
+                    "kernel_source_hash": kernel_source_hash("realspace")}
         print(f"[bench] kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
     cpu = rel_l2 = None

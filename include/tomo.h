@@ -97,18 +97,18 @@ typedef struct {
   int32_t weight_mode;    /* tomo_weight_mode */
   int32_t plane_dtype;    /* tomo_dtype of the plane stack */
   int32_t angle_batch;    /* views per internal batch of tomo_reconstruct; 0 -> automatic */
-  int32_t fourier;        /* workspace of tomo_fourier_reconstruct (needs n_vox in the FFT
-                             sizes below): 0 none; 1 the gridding operator, built here (8 bytes
+  int32_t fourier;        /* workspace of tomo_fourier_reconstruct (needs n_vox among the
+                             FFT sizes below): 0 none; 1 the gridding operator, built here (8 bytes
                              per non-zero trilinear weight, at most 64 n M^2 bytes), used as a
                              gather per call; 2 a per-call splat with 64-bit integer atomics
                              (16 (N+1)^3 bytes) */
   int32_t tune;           /* 1: time the gridding variants on a batch of stacks at plan time
                              and keep the fastest: 4 or 8 voxel rows per thread, and for
                              views in general frames also 8x8x8 cubic tiles and the near-axis
-                             box kernel (footprints of 16 x 4 x 16 or 16 x 2 x 16 voxel tiles
+                             box kernel (footprints of 16 x 8, 4 or 2 x 16 voxel tiles
                              fetched straight into LDS); 0: 8 rows; 2: cubic tiles for general
-                             frames; 3: the near-axis box kernel (4 rows) for general frames
-                             (2 and 3 keep 8 rows for single-axis plans).  Single-axis plans
+                             frames; 3, 4, 5: the near-axis box kernel with 4, 8, 2 rows for
+                             general frames (2 to 5 keep 8 rows for single-axis plans).  Single-axis plans
                              give identical results either way; for other frames the choice
                              moves only the FP32 rounding */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
@@ -125,7 +125,7 @@ typedef struct {
  *   stream hipStream_t the plan's set-up work runs on (synchronised before return)
  *   out    receives the plan; untouched on error.
  * Supported: M every 2^a 3^b 5^c in [16, 256] (others: TOMO_EUNSUPPORTED); N in [2, 1024];
- * K in [1, 2N]; with fourier = 1 or 2 also N in {16, 32, 48, 64, 80, 96, 128, 256}.  Single-axis
+ * K in [1, 2N]; with fourier = 1 or 2 also N = 2^a 3^b 5^c in [16, 256].  Single-axis
  * plans whose stack rows are whole 16-byte chunks (M a multiple of 4, or of 8 for 16-bit
  * planes, and M - N even) use the single-axis gridding kernel; the others use the
  * general-frame kernels (the cubic-tile kernel when M is not such a multiple). */
@@ -263,7 +263,7 @@ const char* tomo_batch_error(tomo_batch_t batch);
 tomo_status tomo_batch_destroy(tomo_batch_t batch);
 
 /* Gridding variant of the plan: voxel rows per thread (4 or 8) of the row-tiled kernels, 0 for
- * cubic tiles, -4 or -2 for the near-axis box kernel with 4 or 2 rows per thread (see tune). */
+ * cubic tiles, -8, -4 or -2 for the near-axis box kernel with 8, 4 or 2 rows per thread (see tune). */
 int32_t tomo_grid_rows(tomo_plan_t plan);
 
 /* Non-zero entries of the plan's Fourier-space gridding operator (0 unless fourier = 1). */

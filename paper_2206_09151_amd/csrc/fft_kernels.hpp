@@ -361,11 +361,21 @@ __global__ __launch_bounds__(Shape<H>::T) void k_planes_split(const float4* __re
   const int xcd = wg & 7, k = wg >> 3;
   // (unsigned: the compiler then needs no sign fix-ups, and keeps the registers it needs low)
   const unsigned per_view = unsigned(npairs) * P * P;
-  const int view = xcd + 8 * int(unsigned(k) / per_view);
-  const unsigned rem = unsigned(k) % per_view;
+  int view;
+  unsigned rem;
+  if (nb == 1 || nb == 2 || nb == 4) {
+    // fewer views than XCDs: view xcd % nb, its (pair, block) units dealt over the 8 / nb XCDs
+    // that share it
+    view = xcd % nb;
+    rem = unsigned(k) * unsigned(8 / nb) + unsigned(xcd / nb);
+    if (rem >= per_view) return;   // whole workgroup leaves together
+  } else {
+    view = xcd + 8 * int(unsigned(k) / per_view);
+    rem = unsigned(k) % per_view;
+    if (view >= nb) return;        // whole workgroup leaves together
+  }
   const int p = int(rem / (P * P));
   const unsigned blk = rem % (P * P);
-  if (view >= nb) return;   // whole workgroup leaves together
   const int p1 = int(blk / P), p2 = int(blk % P);
   const int t = threadIdx.x;
   const int n2 = t % H;
@@ -501,8 +511,12 @@ hipError_t spectra_split(const SpectraLaunch& a) {
 
 template <int H, int P, class OutT>
 hipError_t planes_split_t(const PlanesLaunch& a, const float* scale) {
-  const int nb8 = (a.nb + 7) / 8;
-  hipLaunchKernelGGL((k_planes_split<H, P, OutT>), dim3(8 * P * P * a.npairs * nb8), dim3(Shape<H>::T), 0, a.s, a.q,
+  // eight XCD columns; for nb = 1, 2, 4 the kernel deals each view's (pair, block) units over
+  // 8 / nb XCDs, otherwise one view per XCD
+  const int per_view = P * P * a.npairs;
+  const int reps = (a.nb == 1 || a.nb == 2 || a.nb == 4) ? 8 / a.nb : 0;
+  const int rows = reps ? (per_view + reps - 1) / reps : per_view * ((a.nb + 7) / 8);
+  hipLaunchKernelGGL((k_planes_split<H, P, OutT>), dim3(8 * rows), dim3(Shape<H>::T), 0, a.s, a.q,
                      a.prop, a.tw, a.tw_h, static_cast<OutT*>(a.stack), a.K, a.npairs, a.nb, scale);
   return hipGetLastError();
 }

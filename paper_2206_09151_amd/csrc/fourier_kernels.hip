@@ -365,24 +365,58 @@ __global__ __launch_bounds__(256) void k_fgather(FourierNormArgs a, const unsign
 }
 
 // ------------------------------------------------------------------ 1D FFT along an axis
-// N = R1 * R2 (R2 | R1), L lines per workgroup, R2 threads per line.
+// N = R1 * R2 (R1 >= R2; when R2 does not divide R1 the last stage-2 slots of some threads
+// are idle), L lines per workgroup (L | N), R2 threads per line.
 template <int N_, int R1_, int R2_, int L_>
 struct AxisShape {
   static constexpr int N = N_, R1 = R1_, R2 = R2_, L = L_;
   static constexpr int T = L * R2;
-  static constexpr int E = R1 / R2;
+  static constexpr int E = (R1 + R2 - 1) / R2;
   static constexpr int LP = L + 1;   // LDS pitch of one axis position (float2)
-  static_assert(R1 * R2 == N && R1 % R2 == 0 && N % L == 0, "axis FFT shape");
+  static_assert(R1 * R2 == N && R1 >= R2 && N % L == 0 && T <= 1024, "axis FFT shape");
 };
 template <int N>
 struct Axis;
 template <> struct Axis<16> : AxisShape<16, 4, 4, 16> {};
+template <> struct Axis<18> : AxisShape<18, 6, 3, 18> {};
+template <> struct Axis<20> : AxisShape<20, 5, 4, 20> {};
+template <> struct Axis<24> : AxisShape<24, 6, 4, 24> {};
+template <> struct Axis<25> : AxisShape<25, 5, 5, 25> {};
+template <> struct Axis<27> : AxisShape<27, 9, 3, 27> {};
+template <> struct Axis<30> : AxisShape<30, 6, 5, 30> {};
 template <> struct Axis<32> : AxisShape<32, 8, 4, 32> {};
+template <> struct Axis<36> : AxisShape<36, 6, 6, 36> {};
+template <> struct Axis<40> : AxisShape<40, 10, 4, 40> {};
+template <> struct Axis<45> : AxisShape<45, 9, 5, 45> {};
 template <> struct Axis<48> : AxisShape<48, 12, 4, 48> {};
+template <> struct Axis<50> : AxisShape<50, 10, 5, 50> {};
+template <> struct Axis<54> : AxisShape<54, 9, 6, 54> {};
+template <> struct Axis<60> : AxisShape<60, 10, 6, 60> {};
 template <> struct Axis<64> : AxisShape<64, 16, 4, 64> {};
+template <> struct Axis<72> : AxisShape<72, 12, 6, 36> {};
+template <> struct Axis<75> : AxisShape<75, 15, 5, 25> {};
 template <> struct Axis<80> : AxisShape<80, 20, 4, 40> {};
+template <> struct Axis<81> : AxisShape<81, 9, 9, 27> {};
+template <> struct Axis<90> : AxisShape<90, 15, 6, 30> {};
 template <> struct Axis<96> : AxisShape<96, 24, 4, 48> {};
+template <> struct Axis<100> : AxisShape<100, 10, 10, 25> {};
+template <> struct Axis<108> : AxisShape<108, 18, 6, 36> {};
+template <> struct Axis<120> : AxisShape<120, 24, 5, 40> {};
+template <> struct Axis<125> : AxisShape<125, 25, 5, 25> {};
 template <> struct Axis<128> : AxisShape<128, 16, 8, 32> {};
+template <> struct Axis<135> : AxisShape<135, 27, 5, 27> {};
+template <> struct Axis<144> : AxisShape<144, 24, 6, 36> {};
+template <> struct Axis<150> : AxisShape<150, 30, 5, 30> {};
+template <> struct Axis<160> : AxisShape<160, 40, 4, 32> {};
+template <> struct Axis<162> : AxisShape<162, 27, 6, 27> {};
+template <> struct Axis<180> : AxisShape<180, 36, 5, 36> {};
+template <> struct Axis<192> : AxisShape<192, 24, 8, 32> {};
+template <> struct Axis<200> : AxisShape<200, 40, 5, 40> {};
+template <> struct Axis<216> : AxisShape<216, 36, 6, 24> {};
+template <> struct Axis<225> : AxisShape<225, 25, 9, 25> {};
+template <> struct Axis<240> : AxisShape<240, 24, 10, 16> {};
+template <> struct Axis<243> : AxisShape<243, 27, 9, 27> {};
+template <> struct Axis<250> : AxisShape<250, 25, 10, 25> {};
 template <> struct Axis<256> : AxisShape<256, 16, 16, 16> {};
 
 // X[s + R1 k2] = sum_r W_R2^(r k2) W_N^(r s) sum_m W_R1^(m s) x[r + R2 m], W = exp(+i 2 pi / .)
@@ -433,6 +467,7 @@ __global__ __launch_bounds__(Axis<N>::T) void k_fft_axis(float2* __restrict__ da
 #pragma unroll
   for (int e = 0; e < A::E; ++e) {
     const int s = r * A::E + e;
+    if (s >= A::R1) continue;
 #pragma unroll
     for (int rr = 0; rr < A::R2; ++rr) y[e][rr] = tile[(s * A::R2 + rr) * A::LP + l];
     Dft<A::R2, true>::run(y[e]);
@@ -441,6 +476,7 @@ __global__ __launch_bounds__(Axis<N>::T) void k_fft_axis(float2* __restrict__ da
 #pragma unroll
   for (int e = 0; e < A::E; ++e) {
     const int s = r * A::E + e;
+    if (s >= A::R1) continue;
 #pragma unroll
     for (int k2 = 0; k2 < A::R2; ++k2) tile[(s + A::R1 * k2) * A::LP + l] = y[e][k2];
   }
@@ -456,12 +492,7 @@ __global__ __launch_bounds__(Axis<N>::T) void k_fft_axis(float2* __restrict__ da
 }
 
 // ------------------------------------------------------------------ launchers
-bool fourier_grid_supported(int N) {
-  switch (N) {
-    case 16: case 32: case 48: case 64: case 80: case 96: case 128: case 256: return true;
-    default: return false;
-  }
-}
+bool fourier_grid_supported(int N) { return launch_fourier_fft3(N, nullptr, nullptr, nullptr, nullptr) != hipErrorInvalidValue; }
 
 hipError_t launch_fourier_filter(const FilterArgs& fa, const ViewGeom* geom, int eq12, float4* filt,
                                  hipStream_t s) {
@@ -505,6 +536,7 @@ hipError_t launch_fourier_op_fill(const FilterArgs& fa, const ViewGeom* geom, in
 
 template <int N>
 static hipError_t fft3_impl(float2* grid, float* vol, const float2* tw, hipStream_t s) {
+  if (!grid) return hipSuccess;   // size query: nothing is launched
   const dim3 blocks(unsigned(size_t(N) * N / Axis<N>::L));
   for (int axis = 0; axis < 3; ++axis) {
     hipLaunchKernelGGL(k_fft_axis<N>, blocks, dim3(Axis<N>::T), 0, s, grid, axis == 2 ? vol : nullptr, tw, axis);
@@ -528,15 +560,49 @@ hipError_t launch_fourier_norm(const FourierNormArgs& a, const unsigned long lon
   return hipGetLastError();
 }
 
+// With grid == nullptr only reports whether N is supported (hipSuccess) or not.
 hipError_t launch_fourier_fft3(int N, float2* grid, const float2* tw, float* vol, hipStream_t s) {
   switch (N) {
     case 16: return fft3_impl<16>(grid, vol, tw, s);
+    case 18: return fft3_impl<18>(grid, vol, tw, s);
+    case 20: return fft3_impl<20>(grid, vol, tw, s);
+    case 24: return fft3_impl<24>(grid, vol, tw, s);
+    case 25: return fft3_impl<25>(grid, vol, tw, s);
+    case 27: return fft3_impl<27>(grid, vol, tw, s);
+    case 30: return fft3_impl<30>(grid, vol, tw, s);
     case 32: return fft3_impl<32>(grid, vol, tw, s);
+    case 36: return fft3_impl<36>(grid, vol, tw, s);
+    case 40: return fft3_impl<40>(grid, vol, tw, s);
+    case 45: return fft3_impl<45>(grid, vol, tw, s);
     case 48: return fft3_impl<48>(grid, vol, tw, s);
+    case 50: return fft3_impl<50>(grid, vol, tw, s);
+    case 54: return fft3_impl<54>(grid, vol, tw, s);
+    case 60: return fft3_impl<60>(grid, vol, tw, s);
     case 64: return fft3_impl<64>(grid, vol, tw, s);
+    case 72: return fft3_impl<72>(grid, vol, tw, s);
+    case 75: return fft3_impl<75>(grid, vol, tw, s);
     case 80: return fft3_impl<80>(grid, vol, tw, s);
+    case 81: return fft3_impl<81>(grid, vol, tw, s);
+    case 90: return fft3_impl<90>(grid, vol, tw, s);
     case 96: return fft3_impl<96>(grid, vol, tw, s);
+    case 100: return fft3_impl<100>(grid, vol, tw, s);
+    case 108: return fft3_impl<108>(grid, vol, tw, s);
+    case 120: return fft3_impl<120>(grid, vol, tw, s);
+    case 125: return fft3_impl<125>(grid, vol, tw, s);
     case 128: return fft3_impl<128>(grid, vol, tw, s);
+    case 135: return fft3_impl<135>(grid, vol, tw, s);
+    case 144: return fft3_impl<144>(grid, vol, tw, s);
+    case 150: return fft3_impl<150>(grid, vol, tw, s);
+    case 160: return fft3_impl<160>(grid, vol, tw, s);
+    case 162: return fft3_impl<162>(grid, vol, tw, s);
+    case 180: return fft3_impl<180>(grid, vol, tw, s);
+    case 192: return fft3_impl<192>(grid, vol, tw, s);
+    case 200: return fft3_impl<200>(grid, vol, tw, s);
+    case 216: return fft3_impl<216>(grid, vol, tw, s);
+    case 225: return fft3_impl<225>(grid, vol, tw, s);
+    case 240: return fft3_impl<240>(grid, vol, tw, s);
+    case 243: return fft3_impl<243>(grid, vol, tw, s);
+    case 250: return fft3_impl<250>(grid, vol, tw, s);
     case 256: return fft3_impl<256>(grid, vol, tw, s);
     default: return hipErrorInvalidValue;
   }

@@ -107,7 +107,7 @@ std::string resolve(const tomo_params* p, Resolved* r) {
   if (p->plane_dtype < 0 || p->plane_dtype > 2) return "plane_dtype must be 0, 1 or 2";
   if (p->angle_batch < 0) return "angle_batch must be >= 0";
   if (p->fourier < 0 || p->fourier > 2) return "fourier must be 0, 1 or 2";
-  if (p->tune < 0 || p->tune > 3) return "tune must be 0, 1, 2 or 3";
+  if (p->tune < 0 || p->tune > 5) return "tune must be in [0, 5]";
   r->N = p->n_vox;
   r->M = p->n_pix ? p->n_pix : p->n_vox;
   if (p->n_pix < 0) return "n_pix must be >= 0";
@@ -157,7 +157,7 @@ std::string supported(const tomo_params* p, const Resolved& r) {
   if (p->fourier && !tomo::fourier_grid_supported(r.N)) {
     char b[160];
     std::snprintf(b, sizeof b,
-                  "fourier = 1 needs n_vox in {16, 32, 48, 64, 80, 96, 128, 256} (got %d)", r.N);
+                  "fourier = 1 or 2 needs n_vox = 2^a 3^b 5^c in [16, 256] (got %d)", r.N);
     return b;
   }
   return "";
@@ -572,10 +572,13 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   // general frames: the cubic tiles when asked for, and always when stack rows cannot be
   // fetched as 16-byte chunks (the row-tiled box kernel would gather every view from memory)
   if ((p->tune == 2 || r.M % vec != 0) && !pl->axis_fast) pl->grid_rows = 0;
-  if (p->tune == 3 && !pl->axis_fast && r.M % vec == 0) pl->grid_rows = tomo::kGridTilt4;
+  if (p->tune >= 3 && !pl->axis_fast && r.M % vec == 0)
+    pl->grid_rows = p->tune == 3 ? tomo::kGridTilt4 : p->tune == 4 ? tomo::kGridTilt8 : tomo::kGridTilt2;
   if (p->tune == 1) {
-    // time the gridding kernel with 4 and 8 voxel rows per thread on a full batch of (zeroed)
-    // stacks and keep the faster; results do not depend on the choice
+    // time the gridding variants on a full batch of (zero) stacks and keep the fastest; results
+    // do not depend on the choice.  Each timed launch follows a plane-kernel launch that writes
+    // the batch's stacks, as in a reconstruction, so that the caches hold what they hold then
+    // (timed on idle caches, variants that re-read stack rows look faster than they are)
     float* d_vol = nullptr;
     hipEvent_t ea = nullptr, eb = nullptr;
     auto tune_fail = [&](hipError_t err) {
@@ -588,20 +591,23 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
     const size_t n3 = size_t(r.N) * r.N * r.N;
     if ((e = dev_alloc(&d_vol, n3)) || (e = hipEventCreateWithFlags(&ea, hipEventDisableSystemFence)) ||
         (e = hipEventCreateWithFlags(&eb, hipEventDisableSystemFence)) ||
-        (e = hipMemsetAsync(pl->d_stack, 0, size_t(r.batch) * stack_view_bytes(r.M, r.K, p->plane_dtype), s)) ||
+        (e = hipMemsetAsync(pl->d_q, 0, size_t(r.batch) * mm * sizeof(float4), s)) ||
+        (e = hipMemsetAsync(d_vol, 0, n3 * sizeof(float), s)) ||
         (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(pl->d_scale), 0x3f800000u, size_t(r.n), s)))
       return tune_fail(e);
     float best = 0.0f;
-    for (int rows : {8, 4, 0, tomo::kGridTilt4, tomo::kGridTilt2}) {
+    for (int rows : {8, 4, 0, tomo::kGridTilt8, tomo::kGridTilt4, tomo::kGridTilt2}) {
       // the cubic tiles and the near-axis box serve general frames only; the row-tiled and
       // near-axis kernels need stack rows of whole 16-byte chunks
       if (rows <= 0 && pl->axis_fast) continue;
       if (rows != 0 && r.M % vec != 0) continue;
       float tot = 0.0f;
       for (int rep = 0; rep < 4; ++rep) {
-        if ((e = hipEventRecord(ea, s)) ||
+        if ((e = tomo::launch_planes(r.M, p->plane_dtype, pl->d_q, pl->d_prop, pl->d_tw_inv, pl->d_stack, r.K,
+                                     r.npairs, r.batch, pl->d_scale, s, pl->d_tw2_inv)) ||
+            (e = hipEventRecord(ea, s)) ||
             (e = tomo::launch_grid(pl->axis_fast, p->plane_dtype, pl->d_stack, pl->d_geom, pl->d_scale, d_vol, r.N,
-                                   r.M, r.K, r.batch, 0, p->ewald ? 0 : 1, s, rows)) ||
+                                   r.M, r.K, r.batch, 1, p->ewald ? 0 : 1, s, rows)) ||
             (e = hipEventRecord(eb, s)) || (e = hipEventSynchronize(eb)))
           return tune_fail(e);
         float ms = 0.0f;

@@ -41,9 +41,9 @@ hipError_t launch_planes(int M, int dtype, const float4* q, const float2* prop, 
 // Trilinear gather of nb stacks into V[N][N][N] (accumulate: V += ..., else V = ...).
 // flat: one plane without depth axis (no Ewald curvature): bilinear in the detector plane.
 // rows: voxel rows per thread (4 or 8) of the row-tiled kernels; for views in general frames
-// (single-axis plans keep the row-tiled kernel) 0 selects the cubic-tile kernel and kGridTilt4 /
-// kGridTilt2 the near-axis LDS-fetch box kernel with 4 / 2 voxel rows per thread.
-constexpr int kGridTilt4 = -4, kGridTilt2 = -2;
+// (single-axis plans keep the row-tiled kernel) 0 selects the cubic-tile kernel and kGridTilt8 /
+// kGridTilt4 / kGridTilt2 the near-axis LDS-fetch box kernel with 8 / 4 / 2 voxel rows per thread.
+constexpr int kGridTilt8 = -8, kGridTilt4 = -4, kGridTilt2 = -2;
 hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
                        float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s, int rows);
 // Plan-time tables.

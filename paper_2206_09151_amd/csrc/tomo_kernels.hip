@@ -1128,6 +1128,8 @@ static hipError_t grid_tilt_dtype(int dtype, const void* stack, const ViewGeom* 
 
 hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewGeom* geom, const float* scale,
                        float* vol, int N, int M, int K, int nb, int accumulate, int flat, hipStream_t s, int rows) {
+  if (rows == kGridTilt8 && !axis_fast)
+    return grid_tilt_dtype<8>(dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   if (rows == kGridTilt4 && !axis_fast)
     return grid_tilt_dtype<4>(dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   if (rows == kGridTilt2 && !axis_fast)

@@ -248,5 +248,15 @@ def size_problem(m: int) -> Problem:
     return Problem(f"size{m}", n_vox, m, 12, dx, lam, sig, 1e-3, 1, mode, dirs, dist, imgs)
 
 
+def fourier_size_problem(n: int) -> Problem:
+    """The Fourier-space form on an n^3 grid (N = M = n), 3 views on the sphere."""
+    dx = 1e-10
+    dirs = scan.uniform_sphere(500 + n, 3)
+    dist = np.full(3, 60e-10)
+    lam, sig = 0.05e-10, 0.1
+    imgs = _born(500 + n, n, n, dx, lam, dirs, dist, sig, count=16)
+    return Problem(f"fsize{n}", n, n, 8, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+
+
 SMALL = ["axis32", "ragged44", "sphere45", "pct64", "sampling32", "oddk16", "m80", "m96", "vaxes32",
          "m256", "m256sph", "m160", "m192", "narrow48", "iin32", "m256iin", "pole24", "m128"]

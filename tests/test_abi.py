@@ -68,7 +68,7 @@ def _plan_status(p, dirs=None, dist=None):
     (dict(epsilon=0.0), "epsilon"),
     (dict(sigma=float("nan")), "sigma"),
     (dict(ewald=2), "ewald"),
-    (dict(tune=4), "tune"),
+    (dict(tune=6), "tune"),
     (dict(weight_mode=7), "weight_mode"),
     (dict(n_planes=100), "n_planes"),
 ])

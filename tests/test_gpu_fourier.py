@@ -161,3 +161,15 @@ def test_fourier_async_equals_sync(mode):
         plan.fourier_reconstruct_async(imgs, vol)
     plan.sync()
     assert np.array_equal(vol.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("n", [18, 25, 27, 45, 60, 75, 81, 100, 125, 135, 150, 162, 180, 200, 216, 225, 240, 243, 250])
+def test_fourier_form_on_every_kind_of_grid_size(n):
+    """The inverse 3D FFT of the Fourier-space form takes every 2,3,5-smooth N in [16, 256]:
+    odd sizes, sizes whose stage-2 radix does not divide the stage-1 radix, and the largest."""
+    prob = _problems.fourier_size_problem(n)
+    got, plan = _run(prob, mode=tomo.FOURIER_SPLAT)
+    want = _oracle(prob)
+    err = _rel(got, want)
+    print(f"fourier N={n}: rel-L2 {err:.3g}", flush=True)
+    assert np.all(np.isfinite(got)) and err <= TOL

@@ -235,7 +235,7 @@ def test_autotuned_gridding_gives_identical_volumes(name):
     out = []
     for tune in (0, 1):
         plan = tomo.Plan(prob.params(tune=tune), prob.dirs, prob.dist, vaxes=prob.vaxes)
-        assert plan.grid_rows in (0, 4, 8, -4, -2)
+        assert plan.grid_rows in (0, 4, 8, -8, -4, -2)
         vol = torch.empty((prob.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
         plan.reconstruct(imgs, vol)
         out.append(vol.cpu().numpy())
@@ -290,14 +290,16 @@ def test_binding_refuses_short_or_mistyped_buffers(dev):
 
 @pytest.mark.parametrize("name", ["sampling32", "iin32", "sphere45", "vaxes32", "m256sph", "m192", "pole24",
                                   "m256iin"])
-def test_near_axis_box_gridding_matches_oracle(name):
-    """The near-axis LDS-fetch box kernel (tune = 3) over general frames: tilted single-axis
-    scans (every footprint fits the box), and directions on the sphere and at the poles (many
-    do not: those views take its global-gather path), whole volume."""
+@pytest.mark.parametrize("tune,rows", [(3, -4), (4, -8), (5, -2)])
+def test_near_axis_box_gridding_matches_oracle(name, tune, rows):
+    """The near-axis LDS-fetch box kernel (tune = 3, 4, 5: 4, 8, 2 voxel rows per thread) over
+    general frames: tilted single-axis scans (every footprint fits the box), and directions on
+    the sphere and at the poles (many do not: those views take its global-gather path), whole
+    volume."""
     tomo = _tomo()
     prob = _problems.make(name)
-    plan = tomo.Plan(prob.params(tune=3, angle_batch=5), prob.dirs, prob.dist, vaxes=prob.vaxes)
-    assert plan.grid_rows == -4
+    plan = tomo.Plan(prob.params(tune=tune, angle_batch=5), prob.dirs, prob.dist, vaxes=prob.vaxes)
+    assert plan.grid_rows == rows
     vol = torch.empty((prob.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
     plan.reconstruct(torch.from_numpy(prob.images).to("cuda:0"), vol)
     want = _oracle_par.reconstruct_views(prob.images.astype(np.float64), prob.dirs, prob.dist,
