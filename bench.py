@@ -101,6 +101,8 @@ def kernel_source_hash(method: str = "realspace") -> str:
     csrc = os.path.join(ROOT, "paper_2206_09151_amd", "csrc")
     if method == "fourier":
         files = ["fft.hpp", "geom.hpp", "fourier_kernels.hip"]
+    elif method == "unet":
+        files = ["unet_internal.hpp", "unet_kernels.hip", "unet_host.hip"]
     else:
         files = ["fft.hpp", "fft_kernels.hpp", "geom.hpp", "tomo_kernels.hip"] + \
             sorted(f for f in os.listdir(csrc) if f.startswith("fft_sizes"))
@@ -703,7 +705,8 @@ def run_unet(args):
                      "unit": "TFLOP/s", "frac": round(achieved / BF16_MFMA_PEAK, 4), "traffic": None,
                      "useful_fp32_equivalent_tflops": round(useful, 2),
                      "note": "BF16 matrix-core flops the convolutions execute per step (hi/lo split "
-                             "included) / whole step time, against the dense BF16 peak"},
+                             "included) / whole step time, against the dense BF16 peak",
+                     "kernel_source_hash": kernel_source_hash("unet")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
