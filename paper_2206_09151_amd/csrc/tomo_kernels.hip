@@ -83,14 +83,19 @@ __device__ __forceinline__ int opaque(int v) {
 // Single-axis views (v = y exactly, M - N even): the detector row of voxel row iy is
 // iy + (M-N)/2 exactly, so the trilinear weights reduce to bilinear ones in (plane, col),
 // shared by the YB voxel rows of a thread.  Per view, the workgroup's 16 x 16 (x, z) tile
-// maps into a rotated square of the (plane, col) grid; its bounding box (at most 24 planes x
-// 24 columns; the column start rounded down to a 16-byte boundary) is staged in LDS for the
-// YB rows, zero outside the stack, so the bilinear taps are plain LDS reads.
+// maps into a rotated square of the (plane, col) grid; its bounding box with every tap (at
+// most 24 planes x 28 columns; the column start rounded down to a 16-byte boundary) is staged
+// in LDS for the YB rows, zero outside the stack, so the bilinear taps are plain LDS reads.
+// Only the view's own box is fetched (17 x 20 at 0 degrees, the full 24 x 28 near 45): over a
+// half-turn scan that is 17% fewer bytes into LDS than the fixed 24 x 28 box.
 //
 // The footprints of FP32, BF16 or FP16 planes are fetched straight into LDS in their
-// storage type.  The staged box is chunk-linear (16-byte chunks, 7 per (row,
-// plane) for FP32, 4 for 16-bit values; no padding), so wave w's
-// i-th load of a view covers chunks 256 i + 64 w + lane, and buffer loads with the LDS
+// storage type.  The staged box is chunk-linear in 16-byte slots: 7 chunks per (row, plane)
+// for FP32; for 16-bit values 4 chunks and a fifth slot that is never fetched, so that a
+// (row, plane) spans 20 dwords rather than 16 and planes lp and lp + 2 of the rotated tap
+// pattern fall on different LDS banks (at 16 dwords a wave's reads met 3.3 bank cycles per
+// half-wave against 1.8 at 20, in a count over the scan's angles).  Wave w's
+// i-th load of a view covers slots 256 i + 64 w + lane, and buffer loads with the LDS
 // destination write them in place (lane l's 16 bytes land 16 l bytes after the wave's LDS
 // base; lanes past the last chunk are switched off and write nothing).  Chunks outside the
 // stack get an offset beyond the buffer's range, which the hardware fills with zeros, so no
@@ -123,8 +128,9 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
                                                        int accumulate, int flat, double hm, double hk) {
   constexpr int VEC = DmaBox<InT>::VEC, BOXW = DmaBox<InT>::BOXW, QN = BOXW / VEC;
   constexpr int ES = int(sizeof(InT));                  // bytes per stored value
-  constexpr int PITCH = BOXW * ES / 4;                  // dwords per staged (row, plane)
-  constexpr int NE = YB * AX_BOXH * QN;                 // chunks per staged view
+  constexpr int QP = ES == 2 ? QN + 1 : QN;             // 16-byte slots per staged (row, plane)
+  constexpr int PITCH = QP * 4;                         // dwords per staged (row, plane)
+  constexpr int NE = YB * AX_BOXH * QP;                 // slots per staged view
   constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
   // 16-bit values: one dword of padding, the pair read may touch the dword after a row's last
   constexpr int PAD = ES == 2 ? 4 : 0;
@@ -150,26 +156,38 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
   // Box origins: lane l of every wave computes the origin of view obase + l (FP64, from
   // the tile corners); per view the workgroup-uniform origin is read out of lane n - obase
   // into scalar registers, so the per-view cost is two lane reads.
-  int obase = -64, lane_c0 = 0, lane_p0 = 0;
-  auto origin = [&](int n, int& c0, int& p0) {
+  // The box of a view: columns c0 .. c0 + cw - 1 (cw a multiple of VEC) and planes
+  // p0 .. p0 + bh - 1, from the tile's corner extremes; the taps of a voxel lie at most one
+  // past the floor of its coordinates, and one more column and plane absorb a last-bit
+  // difference between the corner and the voxel arithmetic (within the 24 x 28 maximum).
+  int obase = -64, lane_c0 = 0, lane_p0 = 0, lane_cw = 0, lane_bh = 0;
+  auto origin = [&](int n, int& c0, int& p0, int& cw, int& bh) {
     if (n >= obase + 64) {
       obase = n;
       const int v = n + lane;
-      int cc = 0, pp = 0;
+      int cc = 0, pp = 0, ww = 0, hh = 0;
       if (v < nb) {
         const int t0 = opaque(tx0), z0 = opaque(tz0);
         const double ax = t0 - c, bx = t0 + GT - 1 - c, az = z0 - c, bz = z0 + GT - 1 - c;
         const ViewGeom& g = geom[v];
         const double cmin = fmin(g.u[0] * ax, g.u[0] * bx) + fmin(g.u[2] * az, g.u[2] * bz) + hm;
+        const double cmax = fmax(g.u[0] * ax, g.u[0] * bx) + fmax(g.u[2] * az, g.u[2] * bz) + hm;
         const double pmin = fmin(g.d[0] * ax, g.d[0] * bx) + fmin(g.d[2] * az, g.d[2] * bz) + hk;
+        const double pmax = fmax(g.d[0] * ax, g.d[0] * bx) + fmax(g.d[2] * az, g.d[2] * bz) + hk;
         cc = int(floor(cmin)) & ~(VEC - 1);
         pp = flat ? 0 : int(floor(pmin));
+        ww = min(BOXW, (int(floor(cmax)) - cc + 3 + VEC - 1) & ~(VEC - 1));
+        hh = flat ? 2 : min(AX_BOXH, int(floor(pmax)) - pp + 3);
       }
       lane_c0 = cc;
       lane_p0 = pp;
+      lane_cw = ww;
+      lane_bh = hh;
     }
     c0 = __builtin_amdgcn_readlane(lane_c0, n - obase);
     p0 = __builtin_amdgcn_readlane(lane_p0, n - obase);
+    cw = __builtin_amdgcn_readlane(lane_cw, n - obase);
+    bh = __builtin_amdgcn_readlane(lane_bh, n - obase);
   };
   // per chunk slot: byte offset from the box origin (rows all present), and for boxes that
   // cross the stack's edge its (plane, column) position and detector-row term
@@ -180,29 +198,30 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = threadIdx.x + 256 * i;
-    const int q = e % QN, pl = (e / QN) % AX_BOXH, j = e / (QN * AX_BOXH);
+    const int q = e % QP, pl = (e / QP) % AX_BOXH, j = e / (QP * AX_BOXH);
     const int row = y0 + j + rowoff;
-    cq[i] = VEC * q;
+    cq[i] = VEC * q;                                    // the spare slot (q = QN) has cq = BOXW >= cw
     cpl[i] = pl;
     crow[i] = (e < NE && y0 + j < N && unsigned(row) < unsigned(M)) ? row * K : -1;
     cfo[i] = rows_in ? unsigned((row * K + pl) * M + VEC * q) * unsigned(ES) : kOutOfRange;
   }
   // slot i exists for every thread below the last load; in the last one only below NE
   auto has = [&](int i) { return NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE; };
-  auto load = [&](int n, int c0, int p0, unsigned* dst) {
+  auto load = [&](int n, int c0, int p0, int cw, int bh, unsigned* dst) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<InT*>(stack + size_t(n) * view_sz), short(0), int(view_sz * ES), 0x00020000);
-    if (rows_in && p0 >= 0 && p0 + AX_BOXH <= K && c0 >= 0 && c0 + BOXW <= M) {
+    // slots outside the view's box fetch nothing (their LDS words are never read)
+    if (rows_in && p0 >= 0 && p0 + bh <= K && c0 >= 0 && c0 + cw <= M) {
       const int so = (p0 * M + c0) * ES;
 #pragma unroll
       for (int i = 0; i < PER; ++i)
-        if (has(i))
+        if (has(i) && cpl[i] < bh && cq[i] < cw)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 1024 * i + wbase), 16,
                                                    int(cfo[i]), so, 0, 0);
     } else {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        if (has(i)) {
+        if (has(i) && cpl[i] < bh && cq[i] < cw) {
           const int pp = p0 + cpl[i], cc = c0 + cq[i];
           const bool ok = crow[i] >= 0 && unsigned(pp) < unsigned(K) && unsigned(cc) < unsigned(M);
           const unsigned off = ok ? unsigned((crow[i] + pp) * M + cc) * unsigned(ES) : kOutOfRange;
@@ -217,10 +236,11 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
 #pragma unroll
   for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
   int oc0 = 0, op0 = 0, oc1 = 0, op1 = 0;              // origins of the views in each buffer
+  int ow0 = 0, oh0 = 0, ow1 = 0, oh1 = 0;              // and their box extents
   // view n from buffer b: wait for this wave's loads of it (and for its own reads of the
   // other buffer), barrier (every wave's share has landed; every wave is done with the
   // other buffer), issue view n + 1 into the other buffer, interpolate
-  auto step = [&](unsigned* bx, int& cb, int& pb, unsigned* other, int& co, int& po, int n) {
+  auto step = [&](unsigned* bx, int& cb, int& pb, unsigned* other, int& co, int& po, int& wo, int& ho, int n) {
     if (n >= nb) return;                                // uniform
     __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
     // a plain barrier: the workgroup fence of __syncthreads is not needed after the wait
@@ -228,8 +248,8 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     if (n + 1 < nb) {
-      origin(n + 1, co, po);
-      load(n + 1, co, po, other);
+      origin(n + 1, co, po, wo, ho);
+      load(n + 1, co, po, wo, ho, other);
     }
     if (live) {
       const ViewGeom& g = geom[n];
@@ -279,12 +299,12 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
     }
   };
   if (nb > 0) {
-    origin(0, oc0, op0);
-    load(0, oc0, op0, box0);
+    origin(0, oc0, op0, ow0, oh0);
+    load(0, oc0, op0, ow0, oh0, box0);
   }
   for (int n0 = 0; n0 < nb; n0 += 2) {
-    step(box0, oc0, op0, box1, oc1, op1, n0);
-    step(box1, oc1, op1, box0, oc0, op0, n0 + 1);
+    step(box0, oc0, op0, box1, oc1, op1, ow1, oh1, n0);
+    step(box1, oc1, op1, box0, oc0, op0, ow0, oh0, n0 + 1);
   }
   if (!live) return;
 #pragma unroll
@@ -507,8 +527,9 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
   constexpr int VEC = DmaBox<InT>::VEC, BOXW = DmaBox<InT>::BOXW, QN = BOXW / VEC;
   constexpr int ES = int(sizeof(InT));                  // bytes per stored value
   constexpr int BR = YB + 4, BH = AX_BOXH;              // rows and planes staged per view
-  constexpr int PITCH = BOXW * ES / 4;                  // dwords per staged (row, plane)
-  constexpr int NE = BR * BH * QN;                      // chunks per staged view
+  constexpr int QP = ES == 2 ? QN + 1 : QN;             // 16-byte slots per (row, plane): one spare for 16-bit
+  constexpr int PITCH = QP * 4;                         // dwords per staged (row, plane)
+  constexpr int NE = BR * BH * QP;                      // slots per staged view
   constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
   constexpr int PAD = ES == 2 ? 4 : 0;                  // 16-bit tap pairs may read one dword past a row
   __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + PAD];
@@ -575,13 +596,15 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = threadIdx.x + 256 * i;
-    const int q = e % QN, pl = (e / QN) % BH, j = e / (QN * BH);
+    const int q = e % QP, pl = (e / QP) % BH, j = e / (QP * BH);
     cq[i] = VEC * q;
     cpl[i] = pl;
-    cj[i] = e < NE ? j : -1;
+    cj[i] = e < NE && q < QN ? j : -1;                  // the spare 16-bit slot is never fetched
     cfo[i] = unsigned((j * K + pl) * M + VEC * q) * unsigned(ES);
   }
-  auto has = [&](int i) { return NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE; };
+  auto has = [&](int i) {
+    return (NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE) && (QP == QN || cq[i] < BOXW);
+  };
   auto load = [&](int n, int c0, int r0, int p0, unsigned* dst) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<InT*>(stack + size_t(n) * view_sz), short(0), int(view_sz * ES), 0x00020000);
