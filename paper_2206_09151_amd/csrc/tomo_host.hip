@@ -578,18 +578,26 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
     // time the gridding variants on a full batch of (zero) stacks and keep the fastest; results
     // do not depend on the choice.  Each timed launch follows a plane-kernel launch that writes
     // the batch's stacks, as in a reconstruction, so that the caches hold what they hold then
-    // (timed on idle caches, variants that re-read stack rows look faster than they are)
+    // (timed on idle caches, variants that re-read stack rows look faster than they are).  The
+    // timed batch takes views spread evenly over the scan: a variant's speed depends on how
+    // many footprints fit its box, which changes along the scan
     float* d_vol = nullptr;
+    ViewGeom* d_gs = nullptr;
     hipEvent_t ea = nullptr, eb = nullptr;
     auto tune_fail = [&](hipError_t err) {
       (void)hipStreamSynchronize(s);
       (void)hipFree(d_vol);
+      (void)hipFree(d_gs);
       if (ea) (void)hipEventDestroy(ea);
       if (eb) (void)hipEventDestroy(eb);
       return cleanup_fail(err, "gridding autotune");
     };
     const size_t n3 = size_t(r.N) * r.N * r.N;
-    if ((e = dev_alloc(&d_vol, n3)) || (e = hipEventCreateWithFlags(&ea, hipEventDisableSystemFence)) ||
+    std::vector<ViewGeom> gs(r.batch);
+    for (int i = 0; i < r.batch; ++i) gs[i] = geo[size_t(i) * r.n / r.batch];
+    if ((e = dev_alloc(&d_vol, n3)) || (e = dev_alloc(&d_gs, size_t(r.batch))) ||
+        (e = hipMemcpyAsync(d_gs, gs.data(), gs.size() * sizeof(ViewGeom), hipMemcpyHostToDevice, s)) ||
+        (e = hipEventCreateWithFlags(&ea, hipEventDisableSystemFence)) ||
         (e = hipEventCreateWithFlags(&eb, hipEventDisableSystemFence)) ||
         (e = hipMemsetAsync(pl->d_q, 0, size_t(r.batch) * mm * sizeof(float4), s)) ||
         (e = hipMemsetAsync(d_vol, 0, n3 * sizeof(float), s)) ||
@@ -606,7 +614,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
         if ((e = tomo::launch_planes(r.M, p->plane_dtype, pl->d_q, pl->d_prop, pl->d_tw_inv, pl->d_stack, r.K,
                                      r.npairs, r.batch, pl->d_scale, s, pl->d_tw2_inv)) ||
             (e = hipEventRecord(ea, s)) ||
-            (e = tomo::launch_grid(pl->axis_fast, p->plane_dtype, pl->d_stack, pl->d_geom, pl->d_scale, d_vol, r.N,
+            (e = tomo::launch_grid(pl->axis_fast, p->plane_dtype, pl->d_stack, d_gs, pl->d_scale, d_vol, r.N,
                                    r.M, r.K, r.batch, 1, p->ewald ? 0 : 1, s, rows)) ||
             (e = hipEventRecord(eb, s)) || (e = hipEventSynchronize(eb)))
           return tune_fail(e);
@@ -620,6 +628,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
       }
     }
     (void)hipFree(d_vol);
+    (void)hipFree(d_gs);
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
   }

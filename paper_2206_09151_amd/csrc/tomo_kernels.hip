@@ -515,8 +515,9 @@ __global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
 // BOXW columns -- is fetched straight into LDS by buffer loads with the LDS destination, as in
 // k_grid_axis_dma: chunk-linear boxes, chunks outside the stack zero-filled by the hardware, two
 // boxes alternating so that view n + 1 is in flight while view n is interpolated (trilinear:
-// eight LDS taps per voxel row).  Per view the box origin and whether the footprint fits are
-// computed one view per lane (FP64, from the tile corners) and read out with readlane; a view
+// eight LDS taps per voxel row).  Per view the box origin, its extent and whether the footprint
+// fits are computed one view per lane (FP64, from the tile corners) and read out with readlane;
+// only the view's own extent is fetched (the kernel is bound by its fetch path), and a view
 // whose footprint does not fit is gathered for that tile straight from global memory.
 template <int YB, class InT>
 __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ stack,
@@ -550,13 +551,14 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
   const int wbase = (threadIdx.x & ~63) * 4;            // this wave's first dword in a box, per load
   const int lane = threadIdx.x & 63;
 
-  // box origin (column rounded down to a 16-byte chunk) and fit of view n, one view per lane
-  int obase = -64, lane_c0 = 0, lane_r0 = 0, lane_p0 = 0, lane_fit = 0;
-  auto origin = [&](int n, int& c0, int& r0, int& p0) -> bool {
+  // box origin (column rounded down to a 16-byte chunk), extent and fit of view n, one view per
+  // lane; the extent is packed as columns | rows << 10 | planes << 20
+  int obase = -64, lane_c0 = 0, lane_r0 = 0, lane_p0 = 0, lane_fit = 0, lane_ext = 0;
+  auto origin = [&](int n, int& c0, int& r0, int& p0, int& ext) -> bool {
     if (n >= obase + 64) {
       obase = n;
       const int v = n + lane;
-      int cc = 0, rr = 0, pp = 0, ft = 0;
+      int cc = 0, rr = 0, pp = 0, ft = 0, ex = 0;
       if (v < nb) {
         const int t0 = opaque(tx0), z0 = opaque(tz0);
         const double lo[3] = {t0 - c, ry0, z0 - c};
@@ -576,17 +578,21 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
         rr = int(floor(rmin));
         pp = flat ? 0 : int(floor(pmin));
         // taps reach floor(max) + 1; one slot of slack for the FP32 rounding of the local coordinates
-        ft = (int(floor(cmax)) + 2 - cc < BOXW) && (int(floor(rmax)) + 2 - rr < BR) &&
-             (flat || int(floor(pmax)) + 2 - pp < BH);
+        const int cn = int(floor(cmax)) + 3 - cc, rn = int(floor(rmax)) + 3 - rr;
+        const int pn = flat ? 2 : int(floor(pmax)) + 3 - pp;
+        ft = cn <= BOXW && rn <= BR && pn <= BH;
+        if (ft) ex = ((cn + VEC - 1) & ~(VEC - 1)) | (rn << 10) | (pn << 20);
       }
       lane_c0 = cc;
       lane_r0 = rr;
       lane_p0 = pp;
       lane_fit = ft;
+      lane_ext = ex;
     }
     c0 = __builtin_amdgcn_readlane(lane_c0, n - obase);
     r0 = __builtin_amdgcn_readlane(lane_r0, n - obase);
     p0 = __builtin_amdgcn_readlane(lane_p0, n - obase);
+    ext = __builtin_amdgcn_readlane(lane_ext, n - obase);
     return __builtin_amdgcn_readlane(lane_fit, n - obase) != 0;
   };
   // per chunk slot: byte offset from the box origin, and its (row, plane, column) in the box
@@ -605,20 +611,23 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
   auto has = [&](int i) {
     return (NE % 256 == 0 || i < PER - 1 || int(threadIdx.x) + 256 * i < NE) && (QP == QN || cq[i] < BOXW);
   };
-  auto load = [&](int n, int c0, int r0, int p0, unsigned* dst) {
+  auto load = [&](int n, int c0, int r0, int p0, int ext, unsigned* dst) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<InT*>(stack + size_t(n) * view_sz), short(0), int(view_sz * ES), 0x00020000);
-    if (r0 >= 0 && r0 + BR <= M && p0 >= 0 && p0 + BH <= K && c0 >= 0 && c0 + BOXW <= M) {
+    // slots outside the view's extent fetch nothing (their LDS words are never read)
+    const int cw = ext & 1023, rh = (ext >> 10) & 1023, bh = ext >> 20;
+    auto in_ext = [&](int i) { return cq[i] < cw && cj[i] < rh && cpl[i] < bh; };
+    if (r0 >= 0 && r0 + rh <= M && p0 >= 0 && p0 + bh <= K && c0 >= 0 && c0 + cw <= M) {
       const int so = ((r0 * K + p0) * M + c0) * ES;
 #pragma unroll
       for (int i = 0; i < PER; ++i)
-        if (has(i))
+        if (has(i) && in_ext(i))
           __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + 1024 * i + wbase), 16, int(cfo[i]), so,
                                                    0, 0);
     } else {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        if (has(i)) {
+        if (has(i) && in_ext(i)) {
           const int row = r0 + cj[i], pp = p0 + cpl[i], cc = c0 + cq[i];
           const bool ok = cj[i] >= 0 && unsigned(row) < unsigned(M) && unsigned(pp) < unsigned(K) &&
                           unsigned(cc) < unsigned(M);
@@ -634,17 +643,18 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
 #pragma unroll
   for (int j = 0; j < YB; ++j) acc[j] = 0.0f;
   int oc0 = 0, or0 = 0, op0 = 0, oc1 = 0, or1 = 0, op1 = 0;   // origins of the views in each buffer
+  int oe0 = 0, oe1 = 0;                                       // their extents
   bool of0 = false, of1 = false;                              // their footprints fit
   auto step = [&](unsigned* bx, int& cb, int& rb, int& pb, bool& fb, unsigned* other, int& co, int& ro, int& po,
-                  bool& fo, int n) {
+                  int& eo, bool& fo, int n) {
     if (n >= nb) return;                                // uniform
     __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     if (n + 1 < nb) {
-      fo = origin(n + 1, co, ro, po);
-      if (fo) load(n + 1, co, ro, po, other);
+      fo = origin(n + 1, co, ro, po, eo);
+      if (fo) load(n + 1, co, ro, po, eo, other);
     }
     if (!live) return;
     const ViewGeom& g = geom[n];
@@ -730,12 +740,12 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
     }
   };
   if (nb > 0) {
-    of0 = origin(0, oc0, or0, op0);
-    if (of0) load(0, oc0, or0, op0, box0);
+    of0 = origin(0, oc0, or0, op0, oe0);
+    if (of0) load(0, oc0, or0, op0, oe0, box0);
   }
   for (int n0 = 0; n0 < nb; n0 += 2) {
-    step(box0, oc0, or0, op0, of0, box1, oc1, or1, op1, of1, n0);
-    step(box1, oc1, or1, op1, of1, box0, oc0, or0, op0, of0, n0 + 1);
+    step(box0, oc0, or0, op0, of0, box1, oc1, or1, op1, oe1, of1, n0);
+    step(box1, oc1, or1, op1, of1, box0, oc0, or0, op0, oe0, of0, n0 + 1);
   }
   if (!live) return;
 #pragma unroll
