@@ -51,6 +51,7 @@ __all__ = [
     "frames", "contrast", "spectrum", "signed_index", "axis_angle_weights",
     "sampling_matrix", "density_weights", "ctf_bracket", "filtered_spectra",
     "plane_depths", "depth_planes", "gather", "reconstruct", "reconstruct_views",
+    "reconstruct_at_voxels",
 ]
 
 RAMP_AXIS = "ramp_axis"
@@ -321,3 +322,50 @@ def reconstruct_views(images, dirs, dist, geo: Geometry, vaxes=None, views=None,
 def reconstruct(images, dirs, dist, geo: Geometry, vaxes=None, voxels=None):
     """Full reconstruction V[z, y, x] (or V at the given voxel indices)."""
     return reconstruct_views(images, dirs, dist, geo, vaxes=vaxes, voxels=voxels)
+
+
+def reconstruct_at_voxels(images, dirs, dist, geo: Geometry, voxels, vaxes=None):
+    """V at the given voxels [P, 3] (iz, iy, ix) with O6 taken at the taps only.
+
+    O1-O5 and the tap positions and weights of O7 are those of reconstruct; the plane
+    value at a tap (plane j, row r, column c) is the inverse DFT of O6 written out at that
+    one point,
+        b_j[r, c] = Re (1/M^2) sum_{ky,kx} P[ky, kx] exp(-i pi lambda z_j (qy^2 + qx^2))
+                                  exp(+i 2 pi (ky r + kx c) / M),
+    summed over kx for every tap as one matrix product with P, then over ky.  No FFT: it
+    costs M^2 per tap instead of K M^2 log M per view, for checks at a few voxels of large
+    volumes (one plane at z = 0 without curvature)."""
+    u, v, d = frames(dirs, vaxes)
+    W = density_weights(u, v, d, geo)
+    g = contrast(np.asarray(images), geo.i_in)
+    P = filtered_spectra(spectrum(g), np.asarray(dist), W, geo)
+    n, m = geo.n_vox, geo.n_pix
+    c = (n - 1) / 2.0
+    vox = np.asarray(voxels)
+    rx, ry, rz = vox[:, 2] - c, vox[:, 1] - c, vox[:, 0] - c
+    q2 = (signed_index(m) / (m * geo.voxel)) ** 2            # [M], by storage index
+    kk = np.arange(m)
+    depths = plane_depths(geo) if geo.ewald else np.zeros(1)
+    out = np.zeros(vox.shape[0])
+    for nv in range(d.shape[0]):
+        f_col = u[nv, 0] * rx + u[nv, 1] * ry + u[nv, 2] * rz + (m - 1) / 2.0
+        f_row = v[nv, 0] * rx + v[nv, 1] * ry + v[nv, 2] * rz + (m - 1) / 2.0
+        if geo.ewald:
+            k = geo.n_planes
+            planes = _lin_taps(d[nv, 0] * rx + d[nv, 1] * ry + d[nv, 2] * rz + (k - 1) / 2.0, k)
+        else:
+            planes = [(np.zeros(vox.shape[0], dtype=np.int64), np.ones(vox.shape[0]))]
+        tp, tr, tc, tw, owner = [], [], [], [], []
+        for ip, wp in planes:
+            for ir, wr in _lin_taps(f_row, m):
+                for ic, wc in _lin_taps(f_col, m):
+                    tp.append(ip), tr.append(ir), tc.append(ic), tw.append(wp * wr * wc)
+                    owner.append(np.arange(vox.shape[0]))
+        tp, tr, tc = np.concatenate(tp), np.concatenate(tr), np.concatenate(tc)
+        tw, owner = np.concatenate(tw), np.concatenate(owner)
+        z = depths[tp]
+        bx = np.exp(-1j * np.pi * geo.wavelength * z[None, :] * q2[:, None] + 2j * np.pi * np.outer(kk, tc) / m)
+        by = np.exp(-1j * np.pi * geo.wavelength * z[None, :] * q2[:, None] + 2j * np.pi * np.outer(kk, tr) / m)
+        vals = np.sum(by * (P[nv] @ bx), axis=0).real / (m * m)
+        out += np.bincount(owner, weights=tw * vals, minlength=vox.shape[0])
+    return out

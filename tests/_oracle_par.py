@@ -41,3 +41,18 @@ def reconstruct_views(images, dirs, dist, geo, vaxes=None, views=None, voxels=No
     for p in parts[1:]:
         out = out + p
     return out
+
+
+def batch_job_at_voxels(job: int, voxels):
+    """Oracle values of job `job` of the batched workload at the given voxels: the job's
+    seeded inputs are generated again here (the generator is deterministic), the images
+    rounded to FP32 as the GPU receives them, and the view sum taken at the voxels' taps
+    (oracle.reconstruct_at_voxels).  Runs in a worker process of a spawn pool."""
+    from threadpoolctl import threadpool_limits
+    from synth import workloads
+    w = workloads.batch_jobs()[job]
+    with threadpool_limits(1):
+        _, dirs, dist, imgs = workloads.make_workload(w)
+        geo = oracle.Geometry(w.n_vox, w.M, w.K, w.voxel, w.wavelength, w.sigma, w.epsilon, ewald=w.ewald,
+                              weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in)
+        return oracle.reconstruct_at_voxels(imgs.astype(np.float32).astype(np.float64), dirs, dist, geo, voxels)

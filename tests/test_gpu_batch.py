@@ -4,7 +4,8 @@ Every replay of the graph must reproduce, bit for bit, what tomo_reconstruct giv
 each job on its own (the kernels and their order per job are the same), with eager
 work and synchronisations between replays; the jobs themselves are checked against
 the FP64 oracle (whole volume for the small problems, sampled voxels for the
-batched-workload jobs with 160/192-pixel detectors)."""
+batched-workload jobs with 160/192-pixel detectors, and for all 64 jobs of the
+benchmarked batch at their full size)."""
 import numpy as np
 import pytest
 
@@ -109,3 +110,51 @@ def test_batched_workload_jobs_match_oracle_at_sampled_voxels():
         print(f"  rel-L2 {rel:.3g}", flush=True)
         assert rel <= 1e-5
     batch.destroy()
+
+
+def test_full_batched_workload_matches_oracle_at_sampled_voxels():
+    """All 64 jobs of the benchmarked batch (N 64-192, 60-240 views, 9807 views in all),
+    launched as one graph exactly as bench.py builds it, against the FP64 oracle at 16
+    seeded voxels per job (rel-L2 and max error <= 1e-5 per job).  The oracle runs in a
+    spawn pool while the GPU works, each worker rebuilding its job's seeded inputs and
+    evaluating the planes at the taps only."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    import _oracle_par
+    from synth import workloads
+    jobs = workloads.batch_jobs()
+    rng = np.random.default_rng(64)
+    vox = [rng.integers(0, w.n_vox, size=(16, 3)) for w in jobs]
+    workers = _oracle_par.host_threads()
+    with ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("spawn")) as pool:
+        # largest jobs first, so that the pool drains evenly
+        order = sorted(range(len(jobs)), key=lambda j: -jobs[j].n_vox ** 3 * jobs[j].n_views)
+        futs = {j: pool.submit(_oracle_par.batch_job_at_voxels, j, vox[j]) for j in order}
+
+        def make(w):
+            _, dirs, dist, imgs = workloads.make_workload(w)
+            return dirs, dist, imgs.astype(np.float32)
+
+        with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+            data = list(ex.map(make, jobs))
+        plans, imgs, vols = [], [], []
+        for w, (dirs, dist, im) in zip(jobs, data):
+            params = tomo.Params(n_vox=w.n_vox, n_angles=w.n_views, voxel_size=w.voxel, wavelength=w.wavelength,
+                                 sigma=w.sigma, epsilon=w.epsilon, ewald=w.ewald, weight_mode=w.weight_mode,
+                                 eps_sampling=w.eps_sampling, i_in=w.i_in, tune=1)
+            plans.append(tomo.Plan(params, dirs, dist))
+            imgs.append(torch.from_numpy(im).to("cuda:0"))
+            vols.append(torch.full((w.n_vox,) * 3, float("nan"), dtype=torch.float32, device="cuda:0"))
+        batch = tomo.Batch(plans, imgs, vols)
+        batch.launch()
+        batch.sync()
+        got = [v.cpu().numpy()[x[:, 0], x[:, 1], x[:, 2]].astype(np.float64) for v, x in zip(vols, vox)]
+        batch.destroy()
+        for p in plans:
+            p.destroy()
+        for j, w in enumerate(jobs):
+            want = futs[j].result()
+            rel = float(np.linalg.norm(got[j] - want) / np.linalg.norm(want))
+            worst = float(np.abs(got[j] - want).max() / np.abs(want).max())
+            assert rel <= 1e-5 and worst <= 1e-5, (j, w.n_vox, w.n_views, w.geometry, rel, worst)
