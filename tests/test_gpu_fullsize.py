@@ -5,7 +5,10 @@ closed with tomo_sync), against the oracle over the whole volume:
 * the 128^3, 180-view diffraction-tomography workload (1 A voxels, lambda 0.0197 A,
   128 depth planes, Gaussian atoms at 40 per 1000 A^3, first-Born images);
 * the 64^3, 90-view CT-limit workload as stated (Ewald curvature on, 64 depth planes,
-  projection approximation + Fresnel images).
+  projection approximation + Fresnel images);
+* the 256^3, 360-view tilted X-ray workload: the whole scan at 64 seeded voxels (the
+  oracle's planes evaluated at the taps only), and one 8-view launch batch at 3000 voxels
+  in each plane storage type.
 
 The oracle's view sum is split over the host's threads (tests/_oracle_par.py).  Bar:
 rel-L2 <= 1e-5 and max|got - ref| <= 1e-5 max|ref|."""
@@ -56,6 +59,20 @@ def test_benchmarked_workload_whole_volume_matches_oracle(workload):
                           ewald=w.ewald, weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in)
     ref = _oracle_par.reconstruct_views(imgs.astype(np.float64), dirs, dist, geo)
     _assert_close(got, ref, 1e-5, workload)
+
+
+def test_xray_jitter_256_whole_scan_matches_oracle_at_sampled_voxels(xray_case):
+    """All 360 views through tomo_reconstruct_async as bench.py runs them (automatic
+    batch, autotuned near-axis gridding), at 64 seeded voxels against the FP64 oracle."""
+    w, dirs, dist, imgs, *_ = xray_case
+    plan, got = _bench_like_run(w, imgs, dirs, dist)
+    print(f"xray_jitter_256: batch {plan.batch}, grid rows {plan.grid_rows}", flush=True)
+    vox = np.random.default_rng(12).integers(0, w.n_vox, size=(64, 3))
+    geo = oracle.Geometry(w.n_vox, w.M, w.K, w.voxel, w.wavelength, w.sigma, w.epsilon, ewald=w.ewald,
+                          weight_mode=w.weight_mode, eps_sampling=w.eps_sampling, i_in=w.i_in)
+    ref = oracle.reconstruct_at_voxels(imgs.astype(np.float64), dirs, dist, geo, vox)
+    _assert_close(got[vox[:, 0], vox[:, 1], vox[:, 2]], ref, 1e-5, "xray_jitter_256 whole scan")
+    plan.destroy()
 
 
 @pytest.fixture(scope="module")
