@@ -141,7 +141,7 @@ def make(name: str) -> Problem:
         imgs = _born(19, N, M, dx, lam, dirs, dist, sig)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs, vaxes=vax)
     if name == "m256":
-        # 256-pixel detector (quadrant-split FFT path) over a small volume, single axis
+        # 256-pixel detector (2 x 2 block-split FFT path) over a small volume, single axis
         n, N, M, K = 6, 48, 256, 48
         dirs = scan.single_axis(n, 180.0, offset_deg=11.0)
         dist = np.full(n, 80e-10)
@@ -157,7 +157,7 @@ def make(name: str) -> Problem:
         imgs = _born(21, N, M, dx, lam, dirs, dist, sig, count=30)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
     if name == "m160":
-        # 160-pixel detector (quadrant path over 80-point transforms), odd K
+        # 160-pixel detector (direct 160-point transforms, 40 values per thread), odd K
         n, N, M, K = 5, 40, 160, 41
         dirs = scan.single_axis(n, 180.0, offset_deg=4.0)
         dist = np.full(n, 70e-10)
@@ -165,7 +165,7 @@ def make(name: str) -> Problem:
         imgs = _born(23, N, M, dx, lam, dirs, dist, sig, count=24)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_axis", dirs, dist, imgs)
     if name == "m192":
-        # 192-pixel detector (quadrant path over 96-point transforms), tilted frames
+        # 192-pixel detector (direct 192-point transforms, 48 values per thread), tilted frames
         n, N, M, K = 4, 48, 192, 48
         dirs = scan.uniform_sphere(24, n)
         dist = np.full(n, 70e-10)
