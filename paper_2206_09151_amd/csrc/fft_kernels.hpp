@@ -346,9 +346,54 @@ __global__ void k_scale_split(const float* __restrict__ l1part, float* __restric
   scale[v] = fp16_scale(tot);
 }
 
+// Input of block (P1, P2) of a 2 x 2 split (M = 2H) at the thread's R1 points: per point
+// the four propagated quadrant values (a, b) enter with sign (-1)^(a P1 + b P2).  The block is
+// a template argument, so the signs fold into the FMAs; the quadrants come by buffer loads whose
+// quadrant offset is a constant scalar operand.
+template <int H, int A, int B, bool NEG>
+__device__ __forceinline__ void split2_term(const __amdgpu_buffer_rsrc_t& rs, int vo, float2 cx, float2 cy,
+                                            float2& acc) {
+  constexpr int M = 2 * H;
+  float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+  float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+  if constexpr (NEG) {
+    c = -c;
+    sn = -sn;
+  }
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, (H * A * M + H * B) * int(sizeof(float4)), 0);
+  acc.x = fmaf(c, __uint_as_float(v[0]), fmaf(sn, __uint_as_float(v[2]), acc.x));
+  acc.y = fmaf(c, __uint_as_float(v[1]), fmaf(sn, __uint_as_float(v[3]), acc.y));
+}
+
+template <class S, int H, int P1, int P2>
+__device__ __forceinline__ void split2_input(const float4* __restrict__ qv, const float2* __restrict__ pr,
+                                             const float2* __restrict__ tw_m, int r, int n2,
+                                             float2 (&x)[S::XN]) {
+  constexpr int M = 2 * H;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(qv), short(0),
+                                                                      M * M * int(sizeof(float4)), 0x00020000);
+  const float2 cx0 = pr[n2], cx1 = pr[n2 + H];
+#pragma unroll
+  for (int m = 0; m < S::R1; ++m) {
+    const int n1 = r + S::R2 * m;
+    const int vo = (n1 * M + n2) * int(sizeof(float4));
+    const float2 cy0 = pr[n1], cy1 = pr[n1 + H];
+    float2 acc = make_float2(0.0f, 0.0f);
+    split2_term<H, 0, 0, false>(rs, vo, cx0, cy0, acc);
+    split2_term<H, 0, 1, P2 != 0>(rs, vo, cx1, cy0, acc);
+    split2_term<H, 1, 0, P1 != 0>(rs, vo, cx0, cy1, acc);
+    split2_term<H, 1, 1, (P1 ^ P2) != 0>(rs, vo, cx1, cy1, acc);
+    const int ti = P1 * n1 + P2 * n2;   // < 2M
+    x[m] = cmul(acc, tw_m[ti >= M ? ti - M : ti]);
+    // one point's loads at a time: registers stay few enough for two workgroups per CU,
+    // whose other waves hide the load latency
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Plane pairs of M x M spectra: workgroup (view, pair, block).
 template <int H, int P, class OutT>
-__global__ __launch_bounds__(Shape<H>::T) void k_planes_split(const float4* __restrict__ q,
+__global__ __launch_bounds__(Shape<H>::T, H == 128 ? 8 : 1) void k_planes_split(const float4* __restrict__ q,
                                                              const float2* __restrict__ prop,
                                                              const float2* __restrict__ tw_m,
                                                              const float2* __restrict__ tw_h,
@@ -385,39 +430,38 @@ __global__ __launch_bounds__(Shape<H>::T) void k_planes_split(const float4* __re
   const int r = r_;
   const float4* qv = q + size_t(view) * M * M;
   const float2* pr = prop + size_t(p) * M;
-  float2 cxs[P];
-#pragma unroll
-  for (int b = 0; b < P; ++b) cxs[b] = pr[n2 + H * b];
   float2 x[S::XN];
+  if constexpr (P == 2) {
+    switch (blk) {   // uniform across the workgroup
+      case 0: split2_input<S, H, 0, 0>(qv, pr, tw_m, r, n2, x); break;
+      case 1: split2_input<S, H, 0, 1>(qv, pr, tw_m, r, n2, x); break;
+      case 2: split2_input<S, H, 1, 0>(qv, pr, tw_m, r, n2, x); break;
+      default: split2_input<S, H, 1, 1>(qv, pr, tw_m, r, n2, x); break;
+    }
+  } else {
+    float2 cxs[P];
 #pragma unroll
-  for (int m = 0; m < S::R1; ++m) {
-    const int n1 = r + S::R2 * m;
-    float2 acc = make_float2(0.0f, 0.0f);
+    for (int b = 0; b < P; ++b) cxs[b] = pr[n2 + H * b];
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      const float2 cy = pr[n1 + H * a];
+    for (int m = 0; m < S::R1; ++m) {
+      const int n1 = r + S::R2 * m;
+      float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
-      for (int b = 0; b < P; ++b) {
-        const float2 cx = cxs[b];
-        const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
-        const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
-        const float4 qq = qv[(n1 + H * a) * M + n2 + H * b];
-        const float2 z = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
-        if constexpr (P == 2) {
-          if ((a & p1) ^ (b & p2)) {
-            acc.x -= z.x;
-            acc.y -= z.y;
-          } else {
-            acc.x += z.x;
-            acc.y += z.y;
-          }
-        } else {
+      for (int a = 0; a < P; ++a) {
+        const float2 cy = pr[n1 + H * a];
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          const float2 cx = cxs[b];
+          const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+          const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+          const float4 qq = qv[(n1 + H * a) * M + n2 + H * b];
+          const float2 z = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
           acc = cadd(acc, cmul(z, split_coef<P>(tw_m, H, (a * p1 + b * p2) % P)));
         }
       }
+      const int ti = p1 * n1 + p2 * n2;   // < 2M
+      x[m] = cmul(acc, tw_m[ti >= M ? ti - M : ti]);
     }
-    const int ti = p1 * n1 + p2 * n2;   // < 2M
-    x[m] = cmul(acc, tw_m[ti >= M ? ti - M : ti]);
   }
   // FP16 planes: per-view power-of-two scale, read before the transform (see k_planes)
   float sc = 1.0f;
