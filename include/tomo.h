@@ -103,14 +103,15 @@ typedef struct {
                              gather per call; 2 a per-call splat with 64-bit integer atomics
                              (16 (N+1)^3 bytes) */
   int32_t tune;           /* 1: time the gridding variants on a batch of stacks at plan time
-                             and keep the fastest: 4 or 8 voxel rows per thread, and for
-                             views in general frames also 8x8x8 cubic tiles and the near-axis
-                             box kernel (footprints of 16 x 8, 4 or 2 x 16 voxel tiles
-                             fetched straight into LDS); 0: 8 rows; 2: cubic tiles for general
-                             frames; 3, 4, 5: the near-axis box kernel with 4, 8, 2 rows for
-                             general frames (2 to 5 keep 8 rows for single-axis plans).  Single-axis plans
-                             give identical results either way; for other frames the choice
-                             moves only the FP32 rounding */
+                             and keep the fastest: 4 or 8 voxel rows per thread (also 2 for
+                             single-axis plans), and for views in general frames also 8x8x8
+                             cubic tiles and the near-axis box kernel (footprints of 16 x 8, 4
+                             or 2 x 16 voxel tiles fetched straight into LDS); 0: 8 rows;
+                             2: cubic tiles for general frames; 3, 4, 5: the near-axis box
+                             kernel with 4, 8, 2 rows for general frames (2 to 5 keep 8 rows
+                             for single-axis plans).  Single-axis plans give identical results
+                             either way; for other frames the choice moves only the FP32
+                             rounding */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
                                  when plan tables + workspace would exceed it */
 } tomo_params;
@@ -262,8 +263,9 @@ tomo_status tomo_batch_sync(tomo_batch_t batch, void* stream);
 const char* tomo_batch_error(tomo_batch_t batch);
 tomo_status tomo_batch_destroy(tomo_batch_t batch);
 
-/* Gridding variant of the plan: voxel rows per thread (4 or 8) of the row-tiled kernels, 0 for
- * cubic tiles, -8, -4 or -2 for the near-axis box kernel with 8, 4 or 2 rows per thread (see tune). */
+/* Gridding variant of the plan: voxel rows per thread (4 or 8, or 2 for single-axis plans) of the
+ * row-tiled kernels, 0 for cubic tiles, -8, -4 or -2 for the near-axis box kernel with 8, 4 or 2
+ * rows per thread (see tune). */
 int32_t tomo_grid_rows(tomo_plan_t plan);
 
 /* Non-zero entries of the plan's Fourier-space gridding operator (0 unless fourier = 1). */

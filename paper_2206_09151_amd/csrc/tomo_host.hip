@@ -604,10 +604,12 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
         (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(pl->d_scale), 0x3f800000u, size_t(r.n), s)))
       return tune_fail(e);
     float best = 0.0f;
-    for (int rows : {8, 4, 0, tomo::kGridTilt8, tomo::kGridTilt4, tomo::kGridTilt2}) {
-      // the cubic tiles and the near-axis box serve general frames only; the row-tiled and
-      // near-axis kernels need stack rows of whole 16-byte chunks
+    for (int rows : {8, 4, 2, 0, tomo::kGridTilt8, tomo::kGridTilt4, tomo::kGridTilt2}) {
+      // the cubic tiles and the near-axis box serve general frames only, 2 rows per thread
+      // (twice the workgroups of 4, for small volumes) single-axis plans only; the row-tiled
+      // and near-axis kernels need stack rows of whole 16-byte chunks
       if (rows <= 0 && pl->axis_fast) continue;
+      if (rows == 2 && !pl->axis_fast) continue;
       if (rows != 0 && r.M % vec != 0) continue;
       float tot = 0.0f;
       for (int rep = 0; rep < 4; ++rep) {

@@ -1105,11 +1105,13 @@ static hipError_t grid_impl(bool axis_fast, const void* stack, const ViewGeom* g
     const int yblocks8 = int((grid.z + 7) / 8 * 8);
     hipLaunchKernelGGL((k_grid_axis_dma<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
                        scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1), 0.5 * (K - 1));
-  } else {
+  } else if constexpr (kYB >= 4) {
     const int tiles = int(grid.x * grid.y);
     const int yblocks8 = int((grid.z + 7) / 8 * 8);
     hipLaunchKernelGGL((k_grid_box<kYB, InT>), dim3(unsigned(tiles * yblocks8)), dim3(256), 0, s, st, geom,
                        scale, vol, N, M, K, nb, accumulate, flat);
+  } else {
+    return hipErrorInvalidValue;   // 2 rows per thread: single-axis plans only
   }
   return hipGetLastError();
 }
@@ -1176,6 +1178,8 @@ hipError_t launch_grid(bool axis_fast, int dtype, const void* stack, const ViewG
     }
   }
   if (rows == 4) return grid_dtype<4>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
+  if (rows == 2 && axis_fast)
+    return grid_dtype<2>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   if (rows == 8) return grid_dtype<8>(axis_fast, dtype, stack, geom, scale, vol, N, M, K, nb, accumulate, flat, s);
   return hipErrorInvalidValue;
 }
