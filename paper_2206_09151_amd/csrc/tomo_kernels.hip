@@ -515,11 +515,12 @@ __global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
 // BOXW columns -- is fetched straight into LDS by buffer loads with the LDS destination, as in
 // k_grid_axis_dma: chunk-linear boxes, chunks outside the stack zero-filled by the hardware, two
 // boxes alternating so that view n + 1 is in flight while view n is interpolated (trilinear:
-// eight LDS taps per voxel row).  Per view the box origin, its extent and whether the footprint
+// eight LDS taps per voxel row; with ONE_BOX a single box, fetched and then interpolated, two
+// barriers per view).  Per view the box origin, its extent and whether the footprint
 // fits are computed one view per lane (FP64, from the tile corners) and read out with readlane;
 // only the view's own extent is fetched (the kernel is bound by its fetch path), and a view
 // whose footprint does not fit is gathered for that tile straight from global memory.
-template <int YB, class InT>
+template <int YB, class InT, bool ONE_BOX>
 __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ stack,
                                                        const ViewGeom* __restrict__ geom,
                                                        const float* __restrict__ scale,
@@ -534,7 +535,7 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
   constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
   constexpr int PAD = ES == 2 ? 4 : 0;                  // 16-bit tap pairs may read one dword past a row
   __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + PAD];
-  __shared__ __attribute__((aligned(16))) unsigned box1[NE * 4 + PAD];
+  __shared__ __attribute__((aligned(16))) unsigned box1[ONE_BOX ? 4 : NE * 4 + PAD];
   const int ntx = (N + GT - 1) / GT;
   const int tiles = ntx * ntx;
   const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
@@ -645,17 +646,15 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
   int oc0 = 0, or0 = 0, op0 = 0, oc1 = 0, or1 = 0, op1 = 0;   // origins of the views in each buffer
   int oe0 = 0, oe1 = 0;                                       // their extents
   bool of0 = false, of1 = false;                              // their footprints fit
-  auto step = [&](unsigned* bx, int& cb, int& rb, int& pb, bool& fb, unsigned* other, int& co, int& ro, int& po,
-                  int& eo, bool& fo, int n) {
-    if (n >= nb) return;                                // uniform
+  // wait for this wave's loads and LDS reads, then for every wave
+  auto sync = [&]() {
     __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (n + 1 < nb) {
-      fo = origin(n + 1, co, ro, po, eo);
-      if (fo) load(n + 1, co, ro, po, eo, other);
-    }
+  };
+  // interpolation of view n from its staged box bx (origin cb, rb, pb; fb: it fits)
+  auto interp = [&](const unsigned* bx, int cb, int rb, int pb, bool fb, int n) {
     if (!live) return;
     const ViewGeom& g = geom[n];
     float inv = 1.0f;
@@ -739,13 +738,36 @@ __global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ s
       }
     }
   };
-  if (nb > 0) {
-    of0 = origin(0, oc0, or0, op0, oe0);
-    if (of0) load(0, oc0, or0, op0, oe0, box0);
-  }
-  for (int n0 = 0; n0 < nb; n0 += 2) {
-    step(box0, oc0, or0, op0, of0, box1, oc1, or1, op1, oe1, of1, n0);
-    step(box1, oc1, or1, op1, of1, box0, oc0, or0, op0, oe0, of0, n0 + 1);
+  // two boxes: view n + 1 is fetched while view n is interpolated, one barrier per view
+  auto step = [&](const unsigned* bx, int& cb, int& rb, int& pb, bool& fb, unsigned* other, int& co, int& ro,
+                  int& po, int& eo, bool& fo, int n) {
+    if (n >= nb) return;                                // uniform
+    sync();
+    if (n + 1 < nb) {
+      fo = origin(n + 1, co, ro, po, eo);
+      if (fo) load(n + 1, co, ro, po, eo, other);
+    }
+    interp(bx, cb, rb, pb, fb, n);
+  };
+  if constexpr (ONE_BOX) {
+    // one box (half the LDS, so more workgroups per CU hide each other's fetches): fetch,
+    // wait, interpolate, two barriers per view
+    for (int n = 0; n < nb; ++n) {
+      if (n > 0) sync();                                // every wave is done with the box
+      of0 = origin(n, oc0, or0, op0, oe0);
+      if (of0) load(n, oc0, or0, op0, oe0, box0);
+      sync();
+      interp(box0, oc0, or0, op0, of0, n);
+    }
+  } else {
+    if (nb > 0) {
+      of0 = origin(0, oc0, or0, op0, oe0);
+      if (of0) load(0, oc0, or0, op0, oe0, box0);
+    }
+    for (int n0 = 0; n0 < nb; n0 += 2) {
+      step(box0, oc0, or0, op0, of0, box1, oc1, or1, op1, oe1, of1, n0);
+      step(box1, oc1, or1, op1, of1, box0, oc0, or0, op0, oe0, of0, n0 + 1);
+    }
   }
   if (!live) return;
 #pragma unroll
@@ -1144,7 +1166,9 @@ static hipError_t grid_tilt_impl(const void* stack, const ViewGeom* geom, const 
   if (M % DmaBox<InT>::VEC != 0 || size_t(K) * M * M * sizeof(InT) > size_t(0x7fffffff)) return hipErrorInvalidValue;
   const int ntx = (N + GT - 1) / GT;
   const int yblocks8 = ((N + YB - 1) / YB + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_grid_tilt_dma<YB, InT>), dim3(unsigned(ntx * ntx * yblocks8)), dim3(256), 0, s,
+  // 4 rows: one box per workgroup, four workgroups per CU (at 105 VGPRs) instead of three with two
+  // boxes: 376 vs 385 us per 8-view launch at 256^3; 8 and 2 rows keep two boxes
+  hipLaunchKernelGGL((k_grid_tilt_dma<YB, InT, YB == 4>), dim3(unsigned(ntx * ntx * yblocks8)), dim3(256), 0, s,
                      static_cast<const InT*>(stack), geom, scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1),
                      flat ? 0.0 : 0.5 * (K - 1));
   return hipGetLastError();
