@@ -1166,9 +1166,10 @@ static hipError_t grid_tilt_impl(const void* stack, const ViewGeom* geom, const 
   if (M % DmaBox<InT>::VEC != 0 || size_t(K) * M * M * sizeof(InT) > size_t(0x7fffffff)) return hipErrorInvalidValue;
   const int ntx = (N + GT - 1) / GT;
   const int yblocks8 = ((N + YB - 1) / YB + 7) / 8 * 8;
-  // 4 rows: one box per workgroup, four workgroups per CU (at 105 VGPRs) instead of three with two
-  // boxes: 376 vs 385 us per 8-view launch at 256^3; 8 and 2 rows keep two boxes
-  hipLaunchKernelGGL((k_grid_tilt_dma<YB, InT, YB == 4>), dim3(unsigned(ntx * ntx * yblocks8)), dim3(256), 0, s,
+  // 4 and 8 rows: one box per workgroup, four workgroups per CU (at 105 / 118 VGPRs) instead of
+  // three / two with two boxes (at 256^3 per 8-view launch: 376 vs 385 us, 363 vs 446 us); 2 rows
+  // keep two boxes
+  hipLaunchKernelGGL((k_grid_tilt_dma<YB, InT, YB >= 4>), dim3(unsigned(ntx * ntx * yblocks8)), dim3(256), 0, s,
                      static_cast<const InT*>(stack), geom, scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1),
                      flat ? 0.0 : 0.5 * (K - 1));
   return hipGetLastError();
