@@ -54,7 +54,7 @@ def parse():
                     help="dt_ewald_128 | ct_pct_64 | xray_jitter_256 | batch64 (64 uneven jobs in one graph) | "
                          "unet128 (training step of the artefact-correction network at 128^3) | "
                          "unet_pairs (the network trained on 2000 seeded 128^3 pairs, 30 vs 720 views, and "
-                         "judged on 200 held-out pairs)")
+                         "evaluated on 200 held-out pairs)")
     ap.add_argument("--pairs", type=int, default=0, help="unet_pairs: training pairs (0: 2000)")
     ap.add_argument("--held-out", type=int, default=0, help="unet_pairs: held-out pairs (0: 200)")
     ap.add_argument("--epochs", type=int, default=10, help="unet_pairs: passes over the training pairs")
