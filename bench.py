@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--angle-batch", type=int, default=0)
     ap.add_argument("--tune", type=int, default=1, choices=[0, 1, 2, 3, 4, 5],
                     help="gridding variant: 0 fixed, 1 autotuned at plan time (default), 2 cubic tiles, "
-                         "3 / 4 / 5 near-axis box with 4 / 8 / 2 rows (general frames)")
+                         "3 / 4 / 5 near-axis box with 4 / 8 / 2 rows (general frames; single-axis "
+                         "frames keep 8 rows for 2 to 4 and take 2 rows for 5)")
     ap.add_argument("--plane-dtype", default="f32", choices=["f32", "bf16", "fp16"],
                     help="storage type of the plane stacks (interpolation and sums stay FP32)")
     ap.add_argument("--cpu-voxels", type=int, default=0,

@@ -108,10 +108,10 @@ typedef struct {
                              cubic tiles and the near-axis box kernel (footprints of 16 x 8, 4
                              or 2 x 16 voxel tiles fetched straight into LDS); 0: 8 rows;
                              2: cubic tiles for general frames; 3, 4, 5: the near-axis box
-                             kernel with 4, 8, 2 rows for general frames (2 to 5 keep 8 rows
-                             for single-axis plans).  Single-axis plans give identical results
-                             either way; for other frames the choice moves only the FP32
-                             rounding */
+                             kernel with 4, 8, 2 rows for general frames (single-axis plans
+                             keep 8 rows for 2 to 4 and take 2 rows for 5).  Single-axis plans
+                             give identical results either way; for other frames the choice
+                             moves only the FP32 rounding */
   size_t max_workspace_bytes; /* 0 -> unlimited; otherwise tomo_plan fails with TOMO_ENOMEM
                                  when plan tables + workspace would exceed it */
 } tomo_params;

@@ -574,6 +574,7 @@ tomo_status tomo_plan(const tomo_params* p, const double* dirs, const double* va
   if ((p->tune == 2 || r.M % vec != 0) && !pl->axis_fast) pl->grid_rows = 0;
   if (p->tune >= 3 && !pl->axis_fast && r.M % vec == 0)
     pl->grid_rows = p->tune == 3 ? tomo::kGridTilt4 : p->tune == 4 ? tomo::kGridTilt8 : tomo::kGridTilt2;
+  if (p->tune == 5 && pl->axis_fast) pl->grid_rows = 2;
   if (p->tune == 1) {
     // time the gridding variants on a full batch of (zero) stacks and keep the fastest; results
     // do not depend on the choice.  Each timed launch follows a plane-kernel launch that writes

@@ -248,6 +248,24 @@ def test_autotuned_gridding_gives_identical_volumes(name):
         assert np.linalg.norm(out[0] - out[1]) <= 1e-6 * np.linalg.norm(out[0])
 
 
+@pytest.mark.parametrize("name", ["axis32", "ragged44", "pct64", "oddk16", "m128"])
+def test_two_row_single_axis_gridding_is_bitwise_equal(name):
+    """tune = 5 puts single-axis plans on the 2-row gridding tiles; the per-voxel
+    arithmetic is that of the 8-row tiles (tune = 0), so the volumes are bitwise equal."""
+    tomo = _tomo()
+    prob = _problems.make(name)
+    imgs = torch.from_numpy(prob.images).to("cuda:0")
+    out = []
+    for tune, rows in ((0, 8), (5, 2)):
+        plan = tomo.Plan(prob.params(tune=tune), prob.dirs, prob.dist, vaxes=prob.vaxes)
+        assert plan.grid_rows == rows
+        vol = torch.empty((prob.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+        plan.reconstruct(imgs, vol)
+        out.append(vol.cpu().numpy())
+        plan.destroy()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("name", ["sphere45", "vaxes32", "m256sph", "m192", "sampling32", "pole24"])
 def test_cubic_tile_gridding_matches_oracle(name):
     """The cubic-tile gridding kernel (tune = 2) over general frames, whole volume."""
