@@ -419,4 +419,119 @@ __device__ __forceinline__ void fft2_block_split(float2 (&x)[S::XN], float* __re
     if (S::has_s(sg * E + e)) Dft<R2, INV>::run(&x[e * R2]);
 }
 
+// ---------------------------------------------------------------- rectangular 2D FFT in LDS
+// An MC x MR block (MC rows, MR columns): column transforms of length MC = R1C * R2C over
+// the MR columns, then row transforms of length MR = R1R * R2R over the MC rows, with one
+// thread count T = MR * R2C = MC * R2R.  Same two-stage split per pass and component-split
+// exchanges as fft2_block_split.  Twiddles come from the MR-point table: W_MC^k = W_MR^(P k)
+// with P = MR / MC.
+//   column pass input:  thread (line = t % MR, r = t / MR) holds x[m] = Z[r + R2C m][line]
+//   row pass output:    thread (sg = t % R2R, y = t / R2R) holds out[e*R2R + k2] =
+//                       b[y][sg*ER + e + R1R*k2]  (valid where sg*ER + e < R1R)
+template <int MC_, int R1C_, int R2C_, int MR_, int R1R_, int R2R_>
+struct RectShape {
+  static constexpr int MC = MC_, R1C = R1C_, R2C = R2C_, MR = MR_, R1R = R1R_, R2R = R2R_;
+  static constexpr int P = MR / MC;
+  static constexpr int T = MR * R2C;
+  static constexpr int EC = (R1C + R2C - 1) / R2C, ER = (R1R + R2R - 1) / R2R;
+  static constexpr int max2(int a, int b) { return a > b ? a : b; }
+  static constexpr int XN = max2(max2(R1C, EC * R2C), max2(R1R, ER * R2R));
+  static constexpr int SPC = R2C * MR + 4;   // exchange pitch per column-pass output s (floats)
+  static constexpr int SPR = R2R * MC + 4;   // exchange pitch per row-pass output s
+  static constexpr int TP = MR + 1;          // transpose pitch
+  static constexpr int LDS_FLOATS = max2(max2(R1C * SPC, MC * TP), R1R * SPR);
+  __device__ __forceinline__ static bool has_c(int s) { return s < R1C; }
+  __device__ __forceinline__ static bool has_r(int s) { return s < R1R; }
+  static_assert(R1C * R2C == MC && R1R * R2R == MR && MR % MC == 0, "factorisations");
+  static_assert(T == MC * R2R && T <= 1024, "one thread count for both passes");
+};
+
+template <class S, bool INV>
+__device__ __forceinline__ void fft2_rect_split(float2 (&x)[S::XN], float* __restrict__ lds,
+                                                const float2* __restrict__ tw) {
+  constexpr int MC = S::MC, R1C = S::R1C, R2C = S::R2C, EC = S::EC, SPC = S::SPC;
+  constexpr int MR = S::MR, R1R = S::R1R, R2R = S::R2R, ER = S::ER, SPR = S::SPR, TP = S::TP, P = S::P;
+  const int t = threadIdx.x;
+  const int line = t % MR;
+  int r_;   // uniform across a wave when MR is a multiple of the wave size
+  if constexpr (MR % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / MR);
+  else r_ = t / MR;
+  const int rc = r_;
+  // ---- column pass, stage 1 (radix R1C over m), twiddle W_MC^(r s) = W_MR^(P r s)
+  Dft<R1C, INV>::run(x);
+#pragma unroll
+  for (int s = 1; s < R1C; ++s) x[s] = cmul(x[s], tw[(P * rc * s) % MR]);
+  // ---- exchange 1: thread (line, sgc = t / MR) gets x[e*R2C + rr] = X1[sgc*EC + e][rr]
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int s = 0; s < R1C; ++s) lds[s * SPC + rc * MR + line] = comp ? x[s].y : x[s].x;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      const int s = rc * EC + e;
+      if (!S::has_c(s)) continue;
+#pragma unroll
+      for (int rr = 0; rr < R2C; ++rr) {
+        const float v = lds[s * SPC + rr * MR + line];
+        if (comp) x[e * R2C + rr].y = v;
+        else x[e * R2C + rr].x = v;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- column pass, stage 2 (radix R2C over rr)
+#pragma unroll
+  for (int e = 0; e < EC; ++e)
+    if (S::has_c(rc * EC + e)) Dft<R2C, INV>::run(&x[e * R2C]);
+  // ---- transpose: (row Y = s + R1C*k2, column line) -> thread (row = t % MC, r = t / MC)
+  // gets columns r + R2R*m of its row
+  const int row = t % MC, rr_ = t / MC;
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      const int s = rc * EC + e;
+      if (!S::has_c(s)) continue;
+#pragma unroll
+      for (int k2 = 0; k2 < R2C; ++k2) lds[(s + R1C * k2) * TP + line] = comp ? x[e * R2C + k2].y : x[e * R2C + k2].x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R1R; ++m) {
+      const float v = lds[row * TP + rr_ + R2R * m];
+      if (comp) x[m].y = v;
+      else x[m].x = v;
+    }
+    __syncthreads();
+  }
+  // ---- row pass, stage 1 (radix R1R), twiddle W_MR^(r s)
+  Dft<R1R, INV>::run(x);
+#pragma unroll
+  for (int s = 1; s < R1R; ++s) x[s] = cmul(x[s], tw[(rr_ * s) % MR]);
+  // ---- exchange 3: thread (sg = t % R2R, y = t / R2R) gets X1[sg*ER + e][rr] of row y
+  const int sg = t % R2R, yy = t / R2R;
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+    for (int s = 0; s < R1R; ++s) lds[s * SPR + rr_ * MC + row] = comp ? x[s].y : x[s].x;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < ER; ++e) {
+      const int s = sg * ER + e;
+      if (!S::has_r(s)) continue;
+#pragma unroll
+      for (int q = 0; q < R2R; ++q) {
+        const float v = lds[s * SPR + q * MC + yy];
+        if (comp) x[e * R2R + q].y = v;
+        else x[e * R2R + q].x = v;
+      }
+    }
+    if (comp == 0) __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < ER; ++e)
+    if (S::has_r(sg * ER + e)) Dft<R2R, INV>::run(&x[e * R2R]);
+}
+
 }  // namespace tomo

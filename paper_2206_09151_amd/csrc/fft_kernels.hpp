@@ -247,6 +247,106 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
   }
 }
 
+// ------------------------------------------------------------------ row-split plane kernels
+// For M = 160 and 192, whose direct transforms hold 40 / 48 values per thread (160: with
+// spills): a radix-P decimation in frequency on the row index only splits the M x M inverse
+// transform into P blocks of H x M (H = M / P):
+//   X[P k1 + p1][k2] = DFT_{H x M}(n1, n2) { w_M^(p1 n1) sum_{a<P} w_P^(a p1) x[n1 + H a][n2] }
+// Workgroup (view, pair, p1) computes the output rows P k1 + p1 with 16 (160) or 24 (192)
+// values per thread: the input terms are formed P times per coefficient (not P^2 times as in
+// the P x P split), and every workgroup writes whole rows.  Measured per view of a
+// single-axis scan: 160: 14.6 us against 20.6 direct; 192: 17.7 against 19.1 (three 64-row
+// blocks, 16 values per thread: 22.7; two workgroups per CU forced by a register bound spill,
+// slower still).
+template <int M>
+struct RowSplit;
+template <> struct RowSplit<160> : RectShape<80, 16, 5, 160, 16, 10> {};   // 800 threads
+template <> struct RowSplit<192> : RectShape<96, 24, 4, 192, 24, 8> {};    // 768 threads
+
+template <int M, class OutT>
+__global__ __launch_bounds__(RowSplit<M>::T) void k_planes_rows(const float4* __restrict__ q,
+                                                                 const float2* __restrict__ prop,
+                                                                 const float2* __restrict__ tw,
+                                                                 OutT* __restrict__ stack, int K, int npairs,
+                                                                 int nb, const float* __restrict__ scale) {
+  using S = RowSplit<M>;
+  constexpr int P = S::P, H = S::MC;
+  __shared__ float lds[S::LDS_FLOATS];
+  const int wg = blockIdx.x;
+  const int xcd = wg & 7, k = wg >> 3;
+  const unsigned per_view = unsigned(npairs) * P;
+  int view;
+  unsigned rem;
+  if (nb == 1 || nb == 2 || nb == 4) {
+    // fewer views than XCDs: view xcd % nb, its (pair, block) units dealt over the 8 / nb XCDs
+    view = xcd % nb;
+    rem = unsigned(k) * unsigned(8 / nb) + unsigned(xcd / nb);
+    if (rem >= per_view) return;   // whole workgroup leaves together
+  } else {
+    view = xcd + 8 * int(unsigned(k) / per_view);
+    rem = unsigned(k) % per_view;
+    if (view >= nb) return;        // whole workgroup leaves together
+  }
+  const int p = int(rem / P), p1 = int(rem % P);
+  const int t = threadIdx.x;
+  const int n2 = t % M;
+  int r_;
+  if constexpr (M % 64 == 0) r_ = __builtin_amdgcn_readfirstlane(t / M);
+  else r_ = t / M;
+  const int r = r_;
+  const float4* qv = q + size_t(view) * M * M;
+  const float2* pr = prop + size_t(p) * M;
+  const float2 cx = pr[n2];
+  float2 x[S::XN];
+#pragma unroll
+  for (int m = 0; m < S::R1C; ++m) {
+    const int n1 = r + S::R2C * m;
+    float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      const float2 cy = pr[n1 + H * a];
+      const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+      const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+      const float4 qq = qv[(n1 + H * a) * M + n2];
+      const float2 z = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
+      if (a == 0) acc = z;
+      else if (P == 2) acc = p1 ? csub(acc, z) : cadd(acc, z);           // w_2^(a p1) = (-1)^(a p1)
+      else acc = cadd(acc, cmul(z, tw[H * ((a * p1) % P)]));            // w_P^(a p1) = w_M^(H a p1)
+    }
+    x[m] = p1 == 0 ? acc : cmul(acc, tw[(p1 * n1) % M]);
+  }
+  // FP16 planes: per-view power-of-two scale, read before the transform (see k_planes)
+  float sc = 1.0f;
+  if constexpr (std::is_same<OutT, __half>::value) {
+    sc = scale[view];
+    asm volatile("" : "+v"(sc));
+  }
+  fft2_rect_split<S, true>(x, lds, tw);
+  const int sg = t % S::R2R, y = t / S::R2R;
+  const int row = P * y + p1;
+  const int pa = p, pb = K - 1 - p;
+  OutT* rowa = stack + ((size_t(view) * M + row) * K + pa) * M;
+  OutT* rowb = stack + ((size_t(view) * M + row) * K + pb) * M;
+#pragma unroll
+  for (int k2 = 0; k2 < S::R2R; ++k2) {
+#pragma unroll
+    for (int e = 0; e < S::ER; ++e) {
+      if (!S::has_r(sg * S::ER + e)) continue;
+      rowa[sg * S::ER + e + S::R1R * k2] = to_store<OutT>(x[e * S::R2R + k2].x * sc);
+    }
+  }
+  if (pb != pa) {
+#pragma unroll
+    for (int k2 = 0; k2 < S::R2R; ++k2) {
+#pragma unroll
+      for (int e = 0; e < S::ER; ++e) {
+        if (!S::has_r(sg * S::ER + e)) continue;
+        rowb[sg * S::ER + e + S::R1R * k2] = to_store<OutT>(x[e * S::R2R + k2].y * sc);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ M = P H (162, 180, 200, 216 ... 256)
 // An M x M block with M > 200 does not fit in one CU's LDS.  One radix-P decimation in
 // frequency on both axes splits it into P^2 independent H x H transforms:
@@ -543,6 +643,29 @@ hipError_t planes_direct(const PlanesLaunch& a) {
   }
 }
 
+template <int M, class OutT>
+hipError_t planes_rows_t(const PlanesLaunch& a, const float* scale) {
+  // eight XCD columns; for nb = 1, 2, 4 the kernel deals each view's (pair, block) units over
+  // 8 / nb XCDs, otherwise one view per XCD
+  constexpr int P = RowSplit<M>::P;
+  const int per_view = P * a.npairs;
+  const int reps = (a.nb == 1 || a.nb == 2 || a.nb == 4) ? 8 / a.nb : 0;
+  const int rows = reps ? (per_view + reps - 1) / reps : per_view * ((a.nb + 7) / 8);
+  hipLaunchKernelGGL((k_planes_rows<M, OutT>), dim3(8 * rows), dim3(RowSplit<M>::T), 0, a.s, a.q, a.prop, a.tw,
+                     static_cast<OutT*>(a.stack), a.K, a.npairs, a.nb, scale);
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t planes_rows(const PlanesLaunch& a) {
+  switch (a.dtype) {
+    case 0: return planes_rows_t<M, float>(a, nullptr);
+    case 1: return planes_rows_t<M, __hip_bfloat16>(a, nullptr);
+    case 2: return a.scale ? planes_rows_t<M, __half>(a, a.scale) : hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int H, int P>
 hipError_t spectra_split(const SpectraLaunch& a) {
   hipLaunchKernelGGL((k_spectra_split<H, P>), dim3(P * P * a.nb), dim3(Shape<H>::T), 0, a.s, a.images, a.filt, a.tw,
@@ -587,6 +710,11 @@ struct FftSize {
 template <int M>
 __host__ FftSize direct_size() {
   return FftSize{M, 1, Shape<M>::T, &spectra_direct<M>, &planes_direct<M>};
+}
+// Direct spectra, row-split planes (the plan's tables are those of a direct size).
+template <int M>
+__host__ FftSize rows_size() {
+  return FftSize{M, 1, Shape<M>::T, &spectra_direct<M>, &planes_rows<M>};
 }
 template <int H, int P>
 __host__ FftSize split_size() {
