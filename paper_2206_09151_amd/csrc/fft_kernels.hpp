@@ -262,6 +262,35 @@ template <int M>
 struct RowSplit;
 template <> struct RowSplit<160> : RectShape<80, 16, 5, 160, 16, 10> {};   // 800 threads
 template <> struct RowSplit<192> : RectShape<96, 24, 4, 192, 24, 8> {};    // 768 threads
+template <> struct RowSplit<256> : RectShape<64, 16, 4, 256, 16, 16> {};   // 1024 threads
+
+// Block p1's input of a row-split plane kernel: x[m] = w_M^(p1 n1) sum_a w_P^(a p1)
+// Y[n1 + H a][n2], n1 = r + R2C m, Y = cos(phi) Q1 + sin(phi) Q2 (phi = phi_x + phi_y);
+// P1 a compile-time block index.
+template <class S, int M, int P1>
+__device__ __forceinline__ void rows_input(const float4* __restrict__ qv, const float2* __restrict__ pr,
+                                           const float2* __restrict__ tw, int r, int n2, float2 (&x)[S::XN]) {
+  constexpr int P = S::P, H = S::MC;
+  const float2 cx = pr[n2];
+#pragma unroll
+  for (int m = 0; m < S::R1C; ++m) {
+    const int n1 = r + S::R2C * m;
+    float2 acc = make_float2(0.0f, 0.0f);
+    StaticFor<0, P>::run([&](auto ca) {
+      constexpr int a = decltype(ca)::value;
+      const float2 cy = pr[n1 + H * a];
+      const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+      const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+      const float4 qq = qv[(n1 + H * a) * M + n2];
+      const float2 z = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
+      if constexpr (a == 0) acc = z;
+      else if constexpr (P == 2 || P == 4) acc = cadd(acc, rot<P, a * P1, true>(z));   // exact: 1, +i, -1, -i
+      else acc = cadd(acc, cmul(z, tw[H * ((a * P1) % P)]));                              // w_P^(a p1) = w_M^(H a p1)
+    });
+    if constexpr (P1 == 0) x[m] = acc;
+    else x[m] = cmul(acc, tw[(P1 * n1) % M]);
+  }
+}
 
 template <int M, class OutT>
 __global__ __launch_bounds__(RowSplit<M>::T) void k_planes_rows(const float4* __restrict__ q,
@@ -271,6 +300,7 @@ __global__ __launch_bounds__(RowSplit<M>::T) void k_planes_rows(const float4* __
                                                                  int nb, const float* __restrict__ scale) {
   using S = RowSplit<M>;
   constexpr int P = S::P, H = S::MC;
+  static_assert(P == 2 || P == 4, "block coefficients of P = 2 and 4 only");
   __shared__ float lds[S::LDS_FLOATS];
   const int wg = blockIdx.x;
   const int xcd = wg & 7, k = wg >> 3;
@@ -296,24 +326,34 @@ __global__ __launch_bounds__(RowSplit<M>::T) void k_planes_rows(const float4* __
   const int r = r_;
   const float4* qv = q + size_t(view) * M * M;
   const float2* pr = prop + size_t(p) * M;
-  const float2 cx = pr[n2];
   float2 x[S::XN];
-#pragma unroll
-  for (int m = 0; m < S::R1C; ++m) {
-    const int n1 = r + S::R2C * m;
-    float2 acc = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int a = 0; a < P; ++a) {
-      const float2 cy = pr[n1 + H * a];
-      const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
-      const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
-      const float4 qq = qv[(n1 + H * a) * M + n2];
-      const float2 z = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
-      if (a == 0) acc = z;
-      else if (P == 2) acc = p1 ? csub(acc, z) : cadd(acc, z);           // w_2^(a p1) = (-1)^(a p1)
-      else acc = cadd(acc, cmul(z, tw[H * ((a * p1) % P)]));            // w_P^(a p1) = w_M^(H a p1)
+  if constexpr (P == 4) {
+    // the block's quarter turns as operand swaps: one instantiation per block
+    switch (p1) {   // uniform across the workgroup
+      case 0: rows_input<S, M, 0>(qv, pr, tw, r, n2, x); break;
+      case 1: rows_input<S, M, 1>(qv, pr, tw, r, n2, x); break;
+      case 2: rows_input<S, M, 2>(qv, pr, tw, r, n2, x); break;
+      default: rows_input<S, M, 3>(qv, pr, tw, r, n2, x); break;
     }
-    x[m] = p1 == 0 ? acc : cmul(acc, tw[(p1 * n1) % M]);
+  } else {
+    // P = 2: the block's sign is a select (one instantiation keeps the registers low)
+    const float2 cx = pr[n2];
+#pragma unroll
+    for (int m = 0; m < S::R1C; ++m) {
+      const int n1 = r + S::R2C * m;
+      float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const float2 cy = pr[n1 + H * a];
+        const float c = cx.x * cy.x - cx.y * cy.y;   // cos(phi_x + phi_y)
+        const float sn = cx.y * cy.x + cx.x * cy.y;  // sin(phi_x + phi_y)
+        const float4 qq = qv[(n1 + H * a) * M + n2];
+        const float2 z = make_float2(c * qq.x + sn * qq.z, c * qq.y + sn * qq.w);
+        if (a == 0) acc = z;
+        else acc = p1 ? csub(acc, z) : cadd(acc, z);   // w_2^(a p1) = (-1)^(a p1)
+      }
+      x[m] = p1 == 0 ? acc : cmul(acc, tw[(p1 * n1) % M]);
+    }
   }
   // FP16 planes: per-view power-of-two scale, read before the transform (see k_planes)
   float sc = 1.0f;
@@ -715,6 +755,11 @@ __host__ FftSize direct_size() {
 template <int M>
 __host__ FftSize rows_size() {
   return FftSize{M, 1, Shape<M>::T, &spectra_direct<M>, &planes_rows<M>};
+}
+// P x P block spectra (H = M / P), row-split planes.
+template <int H, int P>
+__host__ FftSize split_rows_size() {
+  return FftSize{P * H, P, Shape<H>::T, &spectra_split<H, P>, &planes_rows<P * H>};
 }
 template <int H, int P>
 __host__ FftSize split_size() {
