@@ -248,20 +248,21 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
 }
 
 // ------------------------------------------------------------------ row-split plane kernels
-// For M = 160 and 192, whose direct transforms hold 40 / 48 values per thread (160: with
-// spills): a radix-P decimation in frequency on the row index only splits the M x M inverse
-// transform into P blocks of H x M (H = M / P):
+// For M = 160, 192 and 256, whose direct transforms hold 40 / 48 values per thread (160: with
+// spills) or whose block does not fit in one CU's LDS (256): a radix-P decimation in
+// frequency on the row index only splits the M x M inverse transform into P blocks of
+// H x M (H = M / P):
 //   X[P k1 + p1][k2] = DFT_{H x M}(n1, n2) { w_M^(p1 n1) sum_{a<P} w_P^(a p1) x[n1 + H a][n2] }
-// Workgroup (view, pair, p1) computes the output rows P k1 + p1 with 16 (160) or 24 (192)
-// values per thread: the input terms are formed P times per coefficient (not P^2 times as in
-// the P x P split), and every workgroup writes whole rows.  Measured per view of a
-// single-axis scan: 160: 14.6 us against 20.6 direct; 192: 17.7 against 19.1 (three 64-row
-// blocks, 16 values per thread: 22.7; two workgroups per CU forced by a register bound spill,
-// slower still).
+// Workgroup (view, pair, p1) computes the output rows P k1 + p1: the input terms are formed
+// P times per coefficient (not P^2 times as in the P x P split), and every workgroup writes
+// whole rows.  Measured per view of a single-axis scan: 160 (P = 2, 16 values per thread,
+// one workgroup per CU): 14.6 us against 20.6 direct and 17.2 with P = 4; 192 (P = 4,
+// 12 values, two workgroups per CU): 15.6 against 19.1 direct and 17.4 with P = 2; 256
+// (P = 4, 16 values): 308 us per 8-view launch against 357 for the 2 x 2 block split.
 template <int M>
 struct RowSplit;
 template <> struct RowSplit<160> : RectShape<80, 16, 5, 160, 16, 10> {};   // 800 threads
-template <> struct RowSplit<192> : RectShape<96, 24, 4, 192, 24, 8> {};    // 768 threads
+template <> struct RowSplit<192> : RectShape<48, 12, 4, 192, 12, 16> {};   // 768 threads
 template <> struct RowSplit<256> : RectShape<64, 16, 4, 256, 16, 16> {};   // 1024 threads
 
 // Block p1's input of a row-split plane kernel: x[m] = w_M^(p1 n1) sum_a w_P^(a p1)

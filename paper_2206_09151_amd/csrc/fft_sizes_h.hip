@@ -1,4 +1,4 @@
-// Spectra and plane kernels for detector sizes 192 (planes as 2 row blocks), 200 (as 2 x 2 blocks of 100).
+// Spectra and plane kernels for detector sizes 192 (planes as 4 row blocks), 200 (as 2 x 2 blocks of 100).
 #include "fft_sizes.hpp"
 
 namespace tomo {
