@@ -1007,22 +1007,28 @@ __global__ __launch_bounds__(256) void k_grid_cube_dma(const float* __restrict__
         const double lo[3] = {opaque(tx0) - c, opaque(ty0) - c, opaque(tz0) - c};
         const double hi[3] = {lo[0] + (CB_E - 1), lo[1] + (CB_E - 1), lo[2] + (CB_E - 1)};
         const ViewGeom& g = geom[v];
-        double cmin = hm, rmin = hm, pmin = hk, cmax = hm, rmax = hm, pmax = hk;
+        // one detector coordinate at a time (fewer registers live at once)
+        auto extremes = [&](const double* w, double h0, int& fmn, int& fmx) {
+          double mn = h0, mx = h0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          cmin += fmin(g.u[a] * lo[a], g.u[a] * hi[a]);
-          rmin += fmin(g.v[a] * lo[a], g.v[a] * hi[a]);
-          pmin += fmin(g.d[a] * lo[a], g.d[a] * hi[a]);
-          cmax += fmax(g.u[a] * lo[a], g.u[a] * hi[a]);
-          rmax += fmax(g.v[a] * lo[a], g.v[a] * hi[a]);
-          pmax += fmax(g.d[a] * lo[a], g.d[a] * hi[a]);
-        }
-        const int cc = int(floor(cmin)) & ~3;
-        const int rr = int(floor(rmin));
-        const int pp = flat ? 0 : int(floor(pmin));
-        const int ww = min(4 * CD_QN, (int(floor(cmax)) - cc + 3 + 3) & ~3);
-        const int hh = min(CB_R, int(floor(rmax)) - rr + 3);
-        const int dd = flat ? 1 : min(CB_R, int(floor(pmax)) - pp + 3);
+          for (int a = 0; a < 3; ++a) {
+            mn += fmin(w[a] * lo[a], w[a] * hi[a]);
+            mx += fmax(w[a] * lo[a], w[a] * hi[a]);
+          }
+          fmn = int(floor(mn));
+          fmx = int(floor(mx));
+          __builtin_amdgcn_sched_barrier(0);
+        };
+        int cmn, cmx, rmn, rmx, pmn, pmx;
+        extremes(g.u, hm, cmn, cmx);
+        extremes(g.v, hm, rmn, rmx);
+        extremes(g.d, hk, pmn, pmx);
+        const int cc = cmn & ~3;
+        const int rr = rmn;
+        const int pp = flat ? 0 : pmn;
+        const int ww = min(4 * CD_QN, (cmx - cc + 3 + 3) & ~3);
+        const int hh = min(CB_R, rmx - rr + 3);
+        const int dd = flat ? 1 : min(CB_R, pmx - pp + 3);
         // packed in 12-bit fields, offset by 1024 (rows, planes) and 2048 (columns): a tile
         // corner is at most sqrt(3) (N - 1) / 2 < 887 from the volume centre (N <= 1024), so
         // every origin lies in [-890, 1024 + 887) (M <= 256, K <= 2048)
