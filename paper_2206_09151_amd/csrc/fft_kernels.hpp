@@ -18,6 +18,7 @@
 //               M = P H: for M > 200, whose M x M block does not fit in one CU's LDS, and
 //               for 162, 180 and 200, whose direct transforms would need R1 = 27 to 40
 //               values per thread in registers and spill at the 1000-thread workgroup.
+//   k_planes_rows: the planes of 160, 192 and 256 as P blocks of whole output rows.
 #pragma once
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(RowSplit<M>::T) void k_planes_rows(const float4* __
   }
 }
 
-// ------------------------------------------------------------------ M = P H (162, 180, 200, 216 ... 256)
+// ------------------------------------------------------------------ M = P H (162, 180, 200, 216 ... 256; the planes of 256 use the row split)
 // An M x M block with M > 200 does not fit in one CU's LDS.  One radix-P decimation in
 // frequency on both axes splits it into P^2 independent H x H transforms:
 //   X[P k1 + p1][P k2 + p2] = DFT_H(n1,n2) { w_M^(p1 n1 + p2 n2) sum_{a,b<P} w_P^(a p1 + b p2) x[n1 + H a][n2 + H b] }
