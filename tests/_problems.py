@@ -229,13 +229,13 @@ def smooth_sizes(lo: int = 16, hi: int = 256) -> list:
     return out
 
 
-def size_problem(m: int) -> Problem:
+def size_problem(m: int, n: int = 3) -> Problem:
     """A small problem on an M-pixel detector: a volume of edge N = min(M, 40) or one less
-    (so that both parities of M - N occur), 12 depth planes, 3 views -- single-axis with the
-    axis ramp for even M, directions on the sphere with the isotropic ramp for odd M."""
+    (so that both parities of M - N occur), 12 depth planes, n views (3 unless given) --
+    single-axis with the axis ramp for even M, directions on the sphere with the isotropic
+    ramp for odd M."""
     dx = 1e-10
     n_vox = min(m, 40) - (m % 4 == 2)
-    n = 3
     if m % 2 == 0:
         dirs = scan.single_axis(n, 180.0, offset_deg=5.0 + m % 7)
         mode = "ramp_axis"
@@ -245,7 +245,8 @@ def size_problem(m: int) -> Problem:
     dist = np.full(n, 60e-10)
     lam, sig = 0.05e-10, 0.1
     imgs = _born(300 + m, n_vox, m, dx, lam, dirs, dist, sig, count=16)
-    return Problem(f"size{m}", n_vox, m, 12, dx, lam, sig, 1e-3, 1, mode, dirs, dist, imgs)
+    return Problem(f"size{m}" if n == 3 else f"size{m}x{n}", n_vox, m, 12, dx, lam, sig, 1e-3, 1, mode, dirs, dist,
+                   imgs)
 
 
 def fourier_size_problem(n: int) -> Problem:

@@ -46,6 +46,28 @@ def test_size_plane_stacks_and_reconstruction_match_oracle(m):
     plan.destroy()
 
 
+@pytest.mark.parametrize("m", [160, 192, 256])
+@pytest.mark.parametrize("per_launch", [1, 3, 4, 9])
+def test_row_split_planes_for_every_view_mapping(m, per_launch):
+    """The row-split plane kernels (160, 192, 256) deal a launch's (view, pair, block) units over
+    the XCDs one way for 1, 2 or 4 views and another for more: nine views through launches of
+    1, 3, 4 or 9 views (ragged last launches included), every stack against the oracle."""
+    from paper_2206_09151_amd import tomo
+    pb = _problems.size_problem(m, n=9)
+    plan = tomo.Plan(pb.params(angle_batch=per_launch), pb.dirs, pb.dist)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(pb.images).to(dev)
+    st = torch.full(plan.stack_shape(per_launch), float("nan"), dtype=torch.float32, device=dev)
+    _, ref_st = _oracle_stacks(pb)
+    for first in range(0, pb.n, per_launch):
+        nb = min(per_launch, pb.n - first)
+        plan.backpropagate(img[first:first + nb].contiguous(), first, nb, st)
+        got = st.cpu().numpy()
+        for i in range(nb):
+            assert_close(got[i], ref_st[first + i], 1e-5, (m, per_launch, first + i))
+    plan.destroy()
+
+
 @pytest.mark.parametrize("m", [25, 27, 162, 200, 225, 243, 250])
 def test_size_filtered_spectra_match_oracle(m):
     from paper_2206_09151_amd import tomo
