@@ -87,6 +87,15 @@ def make(name: str) -> Problem:
         lam, sig = 0.1e-10, 0.0
         imgs = _born(13, N, M, dx, lam, dirs, dist, sig)
         return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
+    if name == "sphere70":
+        # 70 directions on the sphere, all in one gridding launch (box origins are formed for
+        # 64 views at a time)
+        n, N, M, K = 70, 20, 24, 20
+        dirs = scan.uniform_sphere(15, n)
+        dist = np.full(n, 30e-10)
+        lam, sig = 0.1e-10, 0.0
+        imgs = _born(15, N, M, dx, lam, dirs, dist, sig)
+        return Problem(name, N, M, K, dx, lam, sig, 1e-3, 1, "ramp_iso", dirs, dist, imgs)
     if name == "pct64":
         n, N, M = 30, 64, 64
         dirs = scan.single_axis(n, 180.0)

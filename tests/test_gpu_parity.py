@@ -283,6 +283,21 @@ def test_cubic_tile_gridding_matches_oracle(name):
     assert_close(got, want, 1e-5, name)
 
 
+def test_cubic_tile_gridding_over_more_than_64_views_in_one_launch():
+    """The FP32 cubic-tile kernel forms the box origins of 64 views at a time; 70 views in one
+    launch take a second round of them."""
+    tomo = _tomo()
+    prob = _problems.make("sphere70")
+    plan = tomo.Plan(prob.params(tune=2, angle_batch=70), prob.dirs, prob.dist, vaxes=prob.vaxes)
+    assert plan.grid_rows == 0 and plan.batch == 70
+    vol = torch.empty((prob.n_vox,) * 3, dtype=torch.float32, device="cuda:0")
+    plan.reconstruct(torch.from_numpy(prob.images).to("cuda:0"), vol)
+    want = oracle.reconstruct(prob.images.astype(np.float64), prob.dirs, prob.dist, prob.oracle_geometry(),
+                              vaxes=prob.vaxes)
+    assert_close(vol.cpu().numpy().astype(np.float64), want, 1e-5, "sphere70")
+    plan.destroy()
+
+
 def test_binding_refuses_short_or_mistyped_buffers(dev):
     """The binding checks element type and size against the plan before the call, so a
     buffer the kernels would overrun never reaches a launch."""
