@@ -419,19 +419,59 @@ __device__ __forceinline__ bf16x8 zwindow(const uint4 c0, const uint4 c1, int dz
   return *reinterpret_cast<const bf16x8*>(&w);
 }
 
-// Weight-gradient partials of a 16 x 16 (co, ci) block over a chunk of tiles:
-// pw[chunk][co][ci][t] = sum_v gm[co][v] in[ci][v + t - 1].  Taps are dealt to the waves by
-// their (dy, dx) group g = 3 dy + dx: wave w takes groups w and w + 4 with all three dz, and
-// waves 0-2 also take group 8 at dz = w (seven taps each, six for wave 3); every wave runs
-// over all rows of the tile, one LDS read of a column's eight z serving the dz taps of a
-// group.  Each 32-voxel step takes three products (hi hi, hi lo, lo hi).  Two workgroups
-// fit a CU (72 KB of LDS each), so one's tile loads overlap the other's products.  The
-// workgroup with ci block 0 also writes the bias partial pb[chunk][co].
-__global__ __launch_bounds__(256, 2) void k_conv_bwd_w_mfma(const float* __restrict__ x, int sx, int cin,
-                                                            const float* __restrict__ g, int sg,
-                                                            const float* __restrict__ y, int sy, int cout, int n,
-                                                            int tiles_per_chunk, float* __restrict__ pw,
-                                                            float* __restrict__ pb) {
+// Weight-gradient partials with the taps dealt by column: a wave takes the nine taps of one
+// dx over a band of consecutive voxel rows, stepping through the band's halo rows, so that one
+// LDS read of a halo row serves the three dy taps of the voxel rows it borders (a window of
+// three A rows stays in registers).  The (dx, rows) bands of the four waves:
+//   wave 0: dx 0 rows 0-5;  wave 1: dx 0 rows 6-7, dx 1 rows 0-3;
+//   wave 2: dx 1 rows 4-7, dx 2 rows 0-1;  wave 3: dx 2 rows 2-7,
+// 54 (tap, row) steps each, at most two dx (18 accumulators) per wave, and 192 LDS reads of
+// 16 bytes per lane and tile (416 when each wave takes whole (dy, dx) tap groups, whose
+// reads serve only their three dz taps: 4.71 against 4.60 ms per training step at 128^3).
+// A tap's two partial sums (its lower rows, its upper rows, each over the chunk's tiles in
+// order) are added once at the end, lower first.  Two workgroups per CU (72 KB of LDS
+// each), so one's tile loads overlap the other's products; the workgroup with ci block 0
+// also writes the bias partial pb[chunk][co].
+template <int RLO, int RHI>
+__device__ __forceinline__ void wgrad_band(f32x4 (&acc)[9], const unsigned short* ah, const unsigned short* al,
+                                           const unsigned short* bh, const unsigned short* bl, int dx, int m,
+                                           int kg) {
+  bf16x8 wa_hi[3], wa_lo[3];   // A rows r % 3 of the window
+#pragma unroll
+  for (int hr = RLO; hr <= RHI + 2; ++hr) {
+    if (hr <= RHI) {
+      wa_hi[hr % 3] = lds8(&ah[(4 * hr + kg) * PA_S + m * 8]);
+      wa_lo[hr % 3] = lds8(&al[(4 * hr + kg) * PA_S + m * 8]);
+    }
+    const int o = (hr * 10 + 2 * kg + dx) * PB_S + m * 8;
+    const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
+    const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
+    const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
+    const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const int r = hr - dy;
+      if (r < RLO || r > RHI) continue;
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+        // the three products of one (tap, row) step, in the order hi hi, hi lo, lo hi
+        const bf16x8 b_hi = zwindow(h0, h1, dz), b_lo = zwindow(l0, l1, dz);
+        f32x4& a = acc[3 * dy + dz];
+        a = mfma32(wa_hi[r % 3], b_hi, a);
+        a = mfma32(wa_hi[r % 3], b_lo, a);
+        a = mfma32(wa_lo[r % 3], b_hi, a);
+      }
+    }
+    // one halo row's reads at a time
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_conv_bwd_w_mfma_cols(const float* __restrict__ x, int sx, int cin,
+                                                                 const float* __restrict__ g, int sg,
+                                                                 const float* __restrict__ y, int sy, int cout,
+                                                                 int n, int tiles_per_chunk, float* __restrict__ pw,
+                                                                 float* __restrict__ pb) {
   constexpr int AS = 32 * PA_S, BS = 100 * PB_S;   // shorts per plane
   __shared__ __attribute__((aligned(16))) unsigned short smem[2 * AS + 2 * BS];
   unsigned short* ah = smem;
@@ -444,20 +484,21 @@ __global__ __launch_bounds__(256, 2) void k_conv_bwd_w_mfma(const float* __restr
   const int nco = cout / 16;
   const int cb = blockIdx.y % nco, ib = blockIdx.y / nco;
   const int ntiles = wtiles(n);
-  // B offsets of this wave's groups: (dy * 10 + dx) halo columns
-  const int g0 = wave, g1 = wave + 4;
-  const int off0 = ((g0 / 3) * 10 + g0 % 3) * PB_S, off1 = ((g1 / 3) * 10 + g1 % 3) * PB_S;
-  const int off8 = (2 * 10 + 2) * PB_S;
-  f32x4 acc[7];
+  // acc0: the wave's first band (dx = wave), acc1: its second (dx = wave + 1; waves 1 and 2)
+  f32x4 acc0[9], acc1[9];
 #pragma unroll
-  for (int j = 0; j < 7; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < 9; ++j) {
+    acc0[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    acc1[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
   float bsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   const int tile_end = min(ntiles, int(blockIdx.x + 1) * tiles_per_chunk);
   for (int tile = blockIdx.x * tiles_per_chunk; tile < tile_end; ++tile) {
     int x0t, y0t, z0t;
     wtile_origin(tile, n, x0t, y0t, z0t);
     // the gradient block is loaded while other waves may still multiply the previous tile;
-    // the input block after it, to bound the registers in flight
+    // the input block after it, to bound the registers in flight (loading the next tile's
+    // blocks during the products instead spills and is slower)
     ATile ra;
     atile_load(ra, g, sg, y, sy, 16 * cb, n, x0t, y0t, z0t);
     __syncthreads();
@@ -466,49 +507,49 @@ __global__ __launch_bounds__(256, 2) void k_conv_bwd_w_mfma(const float* __restr
     btile_load(rb, x, sx, 16 * ib, n, x0t, y0t, z0t);
     btile_store(rb, bh, bl);
     __syncthreads();
-#pragma unroll 2
-    for (int row = 0; row < 8; ++row) {
-      const bf16x8 a_hi = lds8(&ah[(4 * row + kg) * PA_S + m * 8]);
-      const bf16x8 a_lo = lds8(&al[(4 * row + kg) * PA_S + m * 8]);
-      const int base = (row * 10 + 2 * kg) * PB_S + m * 8;
-#pragma unroll
-      for (int gi = 0; gi < 2; ++gi) {
-        const int o = base + (gi ? off1 : off0);
-        const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
-        const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
-        const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
-        const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-          const bf16x8 b_hi = zwindow(h0, h1, dz), b_lo = zwindow(l0, l1, dz);
-          f32x4& a = acc[3 * gi + dz];
-          a = mfma32(a_hi, b_hi, a);
-          a = mfma32(a_hi, b_lo, a);
-          a = mfma32(a_lo, b_hi, a);
-        }
-      }
-      if (wave < 3) {
-        const int o = base + off8;
-        const uint4 h0 = *reinterpret_cast<const uint4*>(&bh[o]);
-        const uint4 h1 = *reinterpret_cast<const uint4*>(&bh[o + PB_S]);
-        const uint4 l0 = *reinterpret_cast<const uint4*>(&bl[o]);
-        const uint4 l1 = *reinterpret_cast<const uint4*>(&bl[o + PB_S]);
-        const bf16x8 b_hi = zwindow(h0, h1, wave), b_lo = zwindow(l0, l1, wave);
-        acc[6] = mfma32(a_hi, b_hi, acc[6]);
-        acc[6] = mfma32(a_hi, b_lo, acc[6]);
-        acc[6] = mfma32(a_lo, b_hi, acc[6]);
-      }
+    if (wave == 0) {
+      wgrad_band<0, 5>(acc0, ah, al, bh, bl, 0, m, kg);
+    } else if (wave == 1) {
+      wgrad_band<6, 7>(acc0, ah, al, bh, bl, 0, m, kg);
+      wgrad_band<0, 3>(acc1, ah, al, bh, bl, 1, m, kg);
+    } else if (wave == 2) {
+      wgrad_band<4, 7>(acc0, ah, al, bh, bl, 1, m, kg);
+      wgrad_band<0, 1>(acc1, ah, al, bh, bl, 2, m, kg);
+    } else {
+      wgrad_band<2, 7>(acc0, ah, al, bh, bl, 2, m, kg);
     }
   }
-  const int ci = 16 * ib + m;
+  // partials through LDS as part[dx][lower / upper rows][tap j][lane], then tap sums of dx = wave
+  f32x4* part = reinterpret_cast<f32x4*>(smem);
+  auto slot = [&](int dx, int upper, int j) { return ((dx * 2 + upper) * 9 + j) * 64 + lane; };
+  __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    if (j == 6 && wave == 3) break;
-    const int tap = j < 6 ? (j % 3) * 9 + (j < 3 ? g0 : g1) : wave * 9 + 8;
+  for (int j = 0; j < 9; ++j) {
+    if (wave == 0) {
+      part[slot(0, 0, j)] = acc0[j];
+    } else if (wave == 1) {
+      part[slot(0, 1, j)] = acc0[j];
+      part[slot(1, 0, j)] = acc1[j];
+    } else if (wave == 2) {
+      part[slot(1, 1, j)] = acc0[j];
+      part[slot(2, 0, j)] = acc1[j];
+    } else {
+      part[slot(2, 1, j)] = acc0[j];
+    }
+  }
+  __syncthreads();
+  if (wave < 3) {
+    const int dx = wave, ci = 16 * ib + m;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int co = 16 * cb + 4 * kg + i;
-      pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + tap] = acc[j][i];
+    for (int j = 0; j < 9; ++j) {
+      const f32x4 tot = part[slot(dx, 0, j)] + part[slot(dx, 1, j)];
+      const int dy = j / 3, dz = j % 3;
+      const int tap = 9 * dz + 3 * dy + dx;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = 16 * cb + 4 * kg + i;
+        pw[((size_t(blockIdx.x) * cout + co) * cin + ci) * 27 + tap] = tot[i];
+      }
     }
   }
   if (ib == 0) {
@@ -987,8 +1028,8 @@ hipError_t conv_bwd_w(int ks, const float* x, int sx, int cin, const float* g, i
     hipLaunchKernelGGL(k_conv_bwd_w_mfma_c1, dim3(unsigned(chunks), unsigned(cout / 16)), dim3(256), 0, s, x, g, sg,
                        y, sy, cout, n, per, pw, pb);
   } else if (ks == 3 && y && mfma_layer(ks, cin, cout) && cin % 16 == 0) {
-    hipLaunchKernelGGL(k_conv_bwd_w_mfma, dim3(unsigned(chunks), unsigned((cout / 16) * (cin / 16))), dim3(256), 0,
-                       s, x, sx, cin, g, sg, y, sy, cout, n, per, pw, pb);
+    hipLaunchKernelGGL(k_conv_bwd_w_mfma_cols, dim3(unsigned(chunks), unsigned((cout / 16) * (cin / 16))), dim3(256),
+                       0, s, x, sx, cin, g, sg, y, sy, cout, n, per, pw, pb);
   } else if (ks == 1 && cout == 1 && cin <= 16 && cin % 4 == 0 && !y) {
     const unsigned nv = unsigned(n) * unsigned(n) * unsigned(n);
     hipLaunchKernelGGL(k_wgrad1x1, dim3(unsigned(chunks)), dim3(256), 0, s, x, sx, cin, g, nv, unsigned(per), pw, pb);
