@@ -221,6 +221,32 @@ def test_range_errors(dev):
         plan.grid(st, -1, 1, torch.zeros((pb.n_vox,) * 3, device=dev))
 
 
+def test_empty_view_range_is_a_no_op(dev):
+    """nb = 0 (also at first = n_angles, the end of the range) launches nothing: outputs keep
+    their contents, even when the buffers passed are empty tensors."""
+    tomo = _tomo()
+    pb = _problems.make("oddk16")
+    plan = _plan(pb, angle_batch=2)
+    img = torch.from_numpy(pb.images).to(dev)
+    st = torch.full(plan.stack_shape(2), 7.0, dtype=torch.float32, device=dev)
+    vol = torch.full((pb.n_vox,) * 3, -3.0, dtype=torch.float32, device=dev)
+    spec = torch.full((2, pb.n_pix, pb.n_pix, 2), 5.0, dtype=torch.float32, device=dev)
+    empty_st = torch.empty(plan.stack_shape(0), dtype=torch.float32, device=dev)
+    for first in (0, 3, pb.n):
+        plan.backpropagate(img, first, 0, st)
+        plan.backpropagate_noalloc(img, first, 0, st)
+        plan.backpropagate(img, first, 0, empty_st)
+        plan.filtered_spectra(img, first, 0, spec)
+        plan.grid(st, first, 0, vol)
+        plan.grid(empty_st, first, 0, vol)
+    torch.cuda.synchronize()
+    assert bool((st == 7.0).all()) and bool((vol == -3.0).all()) and bool((spec == 5.0).all())
+    # a negative count is a range error, not an empty range
+    with pytest.raises(tomo.TomoError) as e:
+        plan.backpropagate(img, 0, -1, st)
+    assert e.value.status == tomo.EINVAL
+
+
 @pytest.mark.parametrize("name", ["axis32", "ragged44", "pct64", "oddk16", "m160", "sphere45"])
 def test_autotuned_gridding_gives_identical_volumes(name):
     """Plan-time autotuning only picks the voxel rows per gridding thread.  On the

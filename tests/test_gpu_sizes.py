@@ -97,3 +97,26 @@ def test_size_16bit_planes_within_rounding_bound(m, dtype, bound):
     print(f"size {m} dtype {dtype}: rel-L2 {rel:.3e}", flush=True)
     assert rel < bound
     plan.destroy()
+
+
+@pytest.mark.parametrize("m", [32, 45, 128, 256])
+def test_single_view_plan_matches_oracle(m):
+    """A scan of one view (the degenerate quadrature: the axis ramp gives it the whole half
+    turn, pi; the isotropic ramp 2|q|): every launch holds one view, so the plane kernels take
+    their one-view XCD mapping and the gridding launches one view; stack and volume against
+    the oracle."""
+    from paper_2206_09151_amd import tomo
+    pb = _problems.size_problem(m, n=1)
+    print(f"size {m}: one view, N={pb.n_vox} K={pb.n_planes} {pb.weight_mode}", flush=True)
+    plan = tomo.Plan(pb.params(), pb.dirs, pb.dist)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(pb.images).to(dev)
+    st = torch.full(plan.stack_shape(1), float("nan"), dtype=torch.float32, device=dev)
+    plan.backpropagate(img, 0, 1, st)
+    vol = torch.full((pb.n_vox,) * 3, float("nan"), dtype=torch.float32, device=dev)
+    plan.reconstruct(img, vol)
+    _, ref_st = _oracle_stacks(pb)
+    assert_close(st.cpu().numpy()[0], ref_st[0], 1e-5, (m, "planes"))
+    ref = oracle.reconstruct(pb.images.astype(np.float64), pb.dirs, pb.dist, pb.oracle_geometry())
+    assert_close(vol.cpu().numpy(), ref, 1e-5, (m, "volume"))
+    plan.destroy()
