@@ -259,12 +259,13 @@ __global__ __launch_bounds__(Shape<M>::T) void k_planes(const float4* __restrict
 // whole rows.  Measured per view of a single-axis scan: 160 (P = 2, 16 values per thread,
 // one workgroup per CU): 14.6 us against 20.6 direct and 17.2 with P = 4; 192 (P = 4,
 // 12 values, two workgroups per CU): 15.6 against 19.1 direct and 17.4 with P = 2; 256
-// (P = 4, 16 values): 308 us per 8-view launch against 357 for the 2 x 2 block split.
+// (P = 2, 32 values, one workgroup per CU): 300 us per 8-view launch against 308 with P = 4
+// (two workgroups per CU, but twice the input terms) and 357 for the 2 x 2 block split.
 template <int M>
 struct RowSplit;
 template <> struct RowSplit<160> : RectShape<80, 16, 5, 160, 16, 10> {};   // 800 threads
 template <> struct RowSplit<192> : RectShape<48, 12, 4, 192, 12, 16> {};   // 768 threads
-template <> struct RowSplit<256> : RectShape<64, 16, 4, 256, 16, 16> {};   // 1024 threads
+template <> struct RowSplit<256> : RectShape<128, 32, 4, 256, 32, 8> {};   // 1024 threads
 
 // Block p1's input of a row-split plane kernel: x[m] = w_M^(p1 n1) sum_a w_P^(a p1)
 // Y[n1 + H a][n2], n1 = r + R2C m, Y = cos(phi) Q1 + sin(phi) Q2 (phi = phi_x + phi_y);

@@ -1,4 +1,4 @@
-// Spectra and plane kernels for detector sizes 216, 240, 250, 256 (planes as 4 row blocks).
+// Spectra and plane kernels for detector sizes 216, 240, 250, 256 (planes as 2 row blocks).
 #include "fft_sizes.hpp"
 
 namespace tomo {

@@ -518,10 +518,14 @@ __global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
 // eight LDS taps per voxel row; with ONE_BOX a single box, fetched and then interpolated, two
 // barriers per view).  Per view the box origin, its extent and whether the footprint
 // fits are computed one view per lane (FP64, from the tile corners) and read out with readlane;
-// only the view's own extent is fetched (the kernel is bound by its fetch path), and a view
-// whose footprint does not fit is gathered for that tile straight from global memory.
+// only the view's own extent is fetched, and a view whose footprint does not fit is gathered
+// for that tile straight from global memory.  The 4-row kernel is held to five waves per SIMD
+// (five workgroups per CU, which its LDS box allows): 360 against 385 us per 8-view launch at
+// 256^3 with FP32 stacks; the 8-row kernel would spill at that bound.
+template <int YB>
+constexpr int tilt_waves_per_eu() { return YB == 4 ? 5 : 1; }
 template <int YB, class InT, bool ONE_BOX>
-__global__ __launch_bounds__(256) void k_grid_tilt_dma(const InT* __restrict__ stack,
+__global__ __launch_bounds__(256, tilt_waves_per_eu<YB>()) void k_grid_tilt_dma(const InT* __restrict__ stack,
                                                        const ViewGeom* __restrict__ geom,
                                                        const float* __restrict__ scale,
                                                        float* __restrict__ vol, int N, int M, int K, int nb,
@@ -1355,9 +1359,9 @@ static hipError_t grid_tilt_impl(const void* stack, const ViewGeom* geom, const 
   if (M % DmaBox<InT>::VEC != 0 || size_t(K) * M * M * sizeof(InT) > size_t(0x7fffffff)) return hipErrorInvalidValue;
   const int ntx = (N + GT - 1) / GT;
   const int yblocks8 = ((N + YB - 1) / YB + 7) / 8 * 8;
-  // 4 and 8 rows: one box per workgroup, four workgroups per CU (at 105 / 118 VGPRs) instead of
-  // three / two with two boxes (at 256^3 per 8-view launch: 376 vs 385 us, 363 vs 446 us); 2 rows
-  // keep two boxes
+  // 4 and 8 rows: one box per workgroup, five / four workgroups per CU (at 88 / 118 VGPRs)
+  // instead of three / two with two boxes (at 256^3 per 8-view launch, before the five-wave
+  // bound on 4 rows: 376 vs 385 us, 363 vs 446 us); 2 rows keep two boxes
   hipLaunchKernelGGL((k_grid_tilt_dma<YB, InT, YB >= 4>), dim3(unsigned(ntx * ntx * yblocks8)), dim3(256), 0, s,
                      static_cast<const InT*>(stack), geom, scale, vol, N, M, K, nb, accumulate, flat, 0.5 * (M - 1),
                      flat ? 0.0 : 0.5 * (K - 1));
