@@ -521,7 +521,9 @@ __global__ __launch_bounds__(256) void k_grid_box(const InT* __restrict__ stack,
 // only the view's own extent is fetched, and a view whose footprint does not fit is gathered
 // for that tile straight from global memory.  The 4-row kernel is held to five waves per SIMD
 // (five workgroups per CU, which its LDS box allows): 360 against 385 us per 8-view launch at
-// 256^3 with FP32 stacks; the 8-row kernel would spill at that bound.
+// 256^3 with FP32 stacks over a tilt-jittered scan (for directions far from the axis, whose
+// footprints often take the global gather, the bound costs time: the autotuner sees both); the
+// 8-row kernel would spill at that bound.
 template <int YB>
 constexpr int tilt_waves_per_eu() { return YB == 4 ? 5 : 1; }
 template <int YB, class InT, bool ONE_BOX>
