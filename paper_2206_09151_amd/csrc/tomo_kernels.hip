@@ -100,9 +100,15 @@ __device__ __forceinline__ int opaque(int v) {
 // base; lanes past the last chunk are switched off and write nothing).  Chunks outside the
 // stack get an offset beyond the buffer's range, which the hardware fills with zeros, so no
 // masks or register staging are needed.  Two box buffers alternate: view n + 1 is in flight
-// while view n is interpolated, and each view takes one barrier.  A 16-bit tap pair (lc, lc + 1)
-// is the 32-bit window at bit 16 (lc & 1) of the two dwords from element 2 (lc >> 1); FP16
-// values are unscaled through the interpolation weights (the per-view scale is a power of two).
+// while view n is interpolated, and each view takes one barrier.  The 4- and 8-row FP32 kernels
+// keep one box instead (fetch, wait, interpolate, two barriers per view): at 4 rows half the
+// LDS lets eight workgroups share a CU instead of seven, so a 128^3 volume's 2048 tiles run in
+// one round rather than 1.14 (32.3 against 34.5 us per 15-view launch); at 8 rows seven instead
+// of three (34.1 against 42.3 us).  The 16-bit 4-row kernel fits eight workgroups with two
+// boxes; at 8 rows one box (eight workgroups instead of five) made the 16-bit kernel slower
+// (50.8 against 47.2 us per 32-view launch).  A 16-bit tap pair (lc, lc + 1) is the 32-bit
+// window at bit 16 (lc & 1) of the two dwords from element 2 (lc >> 1); FP16 values are
+// unscaled through the interpolation weights (the per-view scale is a power of two).
 template <class InT>
 struct DmaBox;
 template <>
@@ -134,8 +140,9 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
   constexpr int PER = (NE + 255) / 256;                 // loads per thread per view
   // 16-bit values: one dword of padding, the pair read may touch the dword after a row's last
   constexpr int PAD = ES == 2 ? 4 : 0;
+  constexpr bool ONE_BOX = YB >= 4 && ES == 4;
   __shared__ __attribute__((aligned(16))) unsigned box0[NE * 4 + PAD];
-  __shared__ __attribute__((aligned(16))) unsigned box1[NE * 4 + PAD];
+  __shared__ __attribute__((aligned(16))) unsigned box1[ONE_BOX ? 4 : NE * 4 + PAD];
   const int ntx = (N + GT - 1) / GT;
   const int tiles = ntx * ntx;
   const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
@@ -240,17 +247,16 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
   // view n from buffer b: wait for this wave's loads of it (and for its own reads of the
   // other buffer), barrier (every wave's share has landed; every wave is done with the
   // other buffer), issue view n + 1 into the other buffer, interpolate
-  auto step = [&](unsigned* bx, int& cb, int& pb, unsigned* other, int& co, int& po, int& wo, int& ho, int n) {
-    if (n >= nb) return;                                // uniform
+  // wait for this wave's loads and LDS reads, then for every wave (a plain barrier: the
+  // workgroup fence of __syncthreads is not needed after the wait)
+  auto sync = [&]() {
     __builtin_amdgcn_s_waitcnt(7 << 4);                 // vmcnt(0) lgkmcnt(0)
-    // a plain barrier: the workgroup fence of __syncthreads is not needed after the wait
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (n + 1 < nb) {
-      origin(n + 1, co, po, wo, ho);
-      load(n + 1, co, po, wo, ho, other);
-    }
+  };
+  // interpolation of view n from its staged box bx (origin column cb, plane pb)
+  auto interp = [&](const unsigned* bx, int cb, int pb, int n) {
     if (live) {
       const ViewGeom& g = geom[n];
       // flat (one plane, K = 1): a zero depth direction gives fp = 0 (hk = 0, origin plane
@@ -298,13 +304,34 @@ __global__ __launch_bounds__(256) void k_grid_axis_dma(const InT* __restrict__ s
       }
     }
   };
-  if (nb > 0) {
-    origin(0, oc0, op0, ow0, oh0);
-    load(0, oc0, op0, ow0, oh0, box0);
-  }
-  for (int n0 = 0; n0 < nb; n0 += 2) {
-    step(box0, oc0, op0, box1, oc1, op1, ow1, oh1, n0);
-    step(box1, oc1, op1, box0, oc0, op0, ow0, oh0, n0 + 1);
+  auto step = [&](unsigned* bx, int& cb, int& pb, unsigned* other, int& co, int& po, int& wo, int& ho, int n) {
+    if (n >= nb) return;                                // uniform
+    sync();
+    if (n + 1 < nb) {
+      origin(n + 1, co, po, wo, ho);
+      load(n + 1, co, po, wo, ho, other);
+    }
+    interp(bx, cb, pb, n);
+  };
+  if constexpr (ONE_BOX) {
+    // one box: every wave is done with the previous view, fetch, every wave's share has
+    // landed, interpolate
+    for (int n = 0; n < nb; ++n) {
+      if (n > 0) sync();
+      origin(n, oc0, op0, ow0, oh0);
+      load(n, oc0, op0, ow0, oh0, box0);
+      sync();
+      interp(box0, oc0, op0, n);
+    }
+  } else {
+    if (nb > 0) {
+      origin(0, oc0, op0, ow0, oh0);
+      load(0, oc0, op0, ow0, oh0, box0);
+    }
+    for (int n0 = 0; n0 < nb; n0 += 2) {
+      step(box0, oc0, op0, box1, oc1, op1, ow1, oh1, n0);
+      step(box1, oc1, op1, box0, oc0, op0, ow0, oh0, n0 + 1);
+    }
   }
   if (!live) return;
 #pragma unroll
